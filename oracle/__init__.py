@@ -1,0 +1,30 @@
+"""FP64 CPU oracle of the VGGT-X memory-efficient aggregator (arXiv 2509.25191, Sec. 3.2).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the GPU library imports, links or calls
+this package; only the test-suite, the smoke check and the benchmark's CPU
+baseline leg use it.  It shares no code with the HIP path: the only thing both
+sides share is the seeded input generator in ``synth`` (random draws and
+storage-format rounding, no aggregator arithmetic).
+
+The oracle is the plain definition of the aggregator forward: every step in
+float64 numpy, exact two-pass softmax, no chunking, no streaming.  The paper
+states that its memory optimisations (dropping unused layer outputs, bfloat16,
+sequential frame chunks) leave the result unchanged apart from precision
+(Sec. 3.2; Sec. 4.3, Tab. 3), so the definition is the reference for every
+precision the library offers.
+
+Parity status by function (what pins each one is listed in tests/test_oracle.py):
+  layer_norm, gelu, linear, attention, block, aggregate, global_block_rows,
+  frame_block_frames: pinned (closed forms, library routines, brute force,
+  invariants).
+  e4m3_encode / e4m3_decode / quantize_rows: pinned (OCP FP8 definition,
+  exhaustive code table, torch.float8_e4m3fn).
+  Agreement of the whole network with a trained VGGT: parity unpinned (no
+  trained weights or worked numeric example exist for this path).
+"""
+from .aggregator import (  # noqa: F401
+    layer_norm, gelu, linear, split_heads, merge_heads, softmax_rows, attention,
+    attention_probs, block, aggregate, global_block_rows, frame_block_frames,
+    frame_bounds, scene_bounds,
+)
+from .fp8 import e4m3_decode, e4m3_encode, quantize_rows, E4M3_MAX  # noqa: F401
