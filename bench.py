@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Throughput of the VGGT-L-shaped aggregator forward on one MI355X.
+
+Workload (default): 24 frame/global attention pairs, C=1024, 16 heads x 64,
+MLP 4096, S=1000 frames x P=1374 tokens (1,374,000 global tokens), global
+attention in FP8 E4M3 (per-128-row-block scales), everything else bfloat16
+with float32 accumulation, outputs of layers 4/11/17/23 kept.  One step is one
+whole aggregator forward over that batch; inputs (tokens N(0,1), weights
+N(0,0.02)) are synthetic, drawn on the device with a seeded generator and
+resident in HBM before timing starts.
+
+Prints one JSON line.  Besides the headline frames/s it reports the global
+attention TFLOP/s of the run (from the library's per-launch HIP events), the
+same kernel's standalone rate in BF16 (S=1000) and FP32 (S=200), peak HBM,
+the roofline of the dominant kernel and the FP64 oracle's throughput on the
+host CPU (extrapolated from a bounded sample).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import synth  # noqa: E402
+from paper_2509_25191_amd import vggtx as vg  # noqa: E402
+
+PEAK_TFLOPS = {"fp8": 5000.0, "bf16": 2500.0, "f32": 157.3}  # MI355X dense MFMA
+PREC = {"fp8": vg.FP8_E4M3, "bf16": vg.BF16, "f32": vg.F32}
+P_TOKENS = 1374
+OUT_LAYERS = (4, 11, 17, 23)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_weights(model, gen, dtype, dev):
+    layers = []
+    C, F = model.dim, model.mlp_hidden
+    shapes = {"ln1_g": (C,), "ln1_b": (C,), "w_qkv": (3 * C, C), "b_qkv": (3 * C,), "w_o": (C, C), "b_o": (C,),
+              "ln2_g": (C,), "ln2_b": (C,), "w_fc1": (F, C), "b_fc1": (F,), "w_fc2": (C, F), "b_fc2": (C,)}
+    for _ in range(model.depth):
+        l = {}
+        for part in ("frame", "global"):
+            blk = {}
+            for name in synth.BLOCK_FIELDS:
+                t = torch.empty(shapes[name], device=dev, dtype=torch.float32).normal_(0.0, 0.02, generator=gen)
+                if name.endswith("_g"):
+                    t += 1.0
+                blk[name] = t.to(dtype)
+            l[part] = blk
+        layers.append(l)
+    return layers
+
+
+def attn_only_rate(h, S, prec, dev, gen):
+    """Standalone global attention over one scene of S frames: TFLOP/s from the library's events."""
+    N, H, D = S * P_TOKENS, 16, 64
+    dt = torch.float32 if prec == vg.F32 else torch.bfloat16
+    q = torch.empty((N, H, D), device=dev, dtype=torch.float32).normal_(0, 0.64, generator=gen).to(dt)
+    k = torch.empty((N, H, D), device=dev, dtype=torch.float32).normal_(0, 0.64, generator=gen).to(dt)
+    v = torch.empty((N, H, D), device=dev, dtype=torch.float32).normal_(0, 1.0, generator=gen).to(dt)
+    o = torch.empty_like(q)
+    ws = torch.empty(max(256, vg.attn_workspace_size(h, [0, N], H, D, prec)), dtype=torch.uint8, device=dev)
+    vg.attn_global(h, q, k, v, o, [0, N], prec, ws=ws)  # untimed first call
+    torch.cuda.synchronize()
+    vg.timing_enable(h, True)
+    vg.attn_global(h, q, k, v, o, [0, N], prec, ws=ws)
+    torch.cuda.synchronize()
+    t = vg.timing_read(h)["attn_global"]
+    vg.timing_enable(h, False)
+    del q, k, v, o, ws
+    torch.cuda.empty_cache()
+    return t["flops"] / (t["ms"] * 1e-3) / 1e12, t["ms"]
+
+
+def cpu_baseline(S, P, C=1024, H=16, F=4096, depth=24):
+    """FP64 oracle throughput on the host, extrapolated to the whole forward
+    from timed pieces: one frame block on one frame; the token-local part of
+    a block (LN, QKV, out-projection, MLP) on a 2048-row slab; global
+    attention of 32 query rows of one head against all S*P keys."""
+    import threadpoolctl
+
+    import oracle
+    rng = np.random.default_rng(0)
+    N = S * P
+    w = synth.gen_block(rng, C, F)
+    w64 = {k: v.astype(np.float64) for k, v in w.items()}
+    x1 = rng.standard_normal((P, C))
+
+    def best(fn, reps=2):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter(); fn(); ts.append(time.perf_counter() - t0)
+        return min(ts)
+
+    t_frame = best(lambda: oracle.block(x1, w64, [(0, P)], H, 1e-6))
+    rows = 2048
+    xs = rng.standard_normal((rows, C))
+
+    def token_local():
+        hh = oracle.layer_norm(xs, w64["ln1_g"], w64["ln1_b"], 1e-6)
+        oracle.linear(hh, w64["w_qkv"], w64["b_qkv"])
+        x1_ = xs + oracle.linear(hh, w64["w_o"], w64["b_o"])
+        h2 = oracle.layer_norm(x1_, w64["ln2_g"], w64["ln2_b"], 1e-6)
+        oracle.linear(oracle.gelu(oracle.linear(h2, w64["w_fc1"], w64["b_fc1"])), w64["w_fc2"], w64["b_fc2"])
+
+    t_tok = best(token_local)
+    qrows = 32
+    q = rng.standard_normal((1, qrows, 64))
+    k = rng.standard_normal((1, N, 64))
+    v = rng.standard_normal((1, N, 64))
+    t_att = best(lambda: oracle.attention(q, k, v), reps=1)
+    per_layer = S * t_frame + (N / rows) * t_tok + (N * H / qrows) * t_att
+    total = depth * per_layer
+    info = threadpoolctl.threadpool_info()
+    cores = max([i.get("num_threads", 1) for i in info] + [1])
+    sample = (f"oracle pieces timed: frame block on 1 frame of {P} tokens ({t_frame:.2f}s), token-local block "
+              f"ops on {rows} rows ({t_tok:.2f}s), global attention of {qrows} query rows x 1 head over {N} keys "
+              f"({t_att:.2f}s); extrapolated x{S} frames, x{N / rows:.0f} slabs, x{N * H / qrows:.0f} row groups, "
+              f"x{depth} layers = {total:.3g}s per forward")
+    return {"value": S / total, "unit": "frames/s", "cores": int(cores), "kind": "oracle", "sample": sample}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--frames", type=int, default=1000)
+    ap.add_argument("--prec", choices=list(PREC), default="fp8")
+    ap.add_argument("--no-extra", action="store_true", help="skip the standalone BF16/FP32 attention rates")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
+              f"(the multi-GPU sharding of the path is a design, not an implementation).", file=sys.stderr)
+        sys.exit(2)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    S, P = args.frames, P_TOKENS
+    model = synth.ModelConfig()
+    prec = PREC[args.prec]
+    wdt = torch.float32 if prec == vg.F32 else torch.bfloat16
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(args.seed)
+    log(f"generating inputs: S={S} P={P} C={model.dim} depth={model.depth} prec={args.prec}")
+    tokens = torch.empty((S, P, model.dim), device=dev, dtype=torch.float32).normal_(0, 1, generator=gen)
+    layers = make_weights(model, gen, wdt, dev)
+    h = vg.Handle(0, dim=model.dim, heads=model.heads, head_dim=model.head_dim, mlp_hidden=model.mlp_hidden,
+                  ln_eps=model.ln_eps, frame_chunk=model.frame_chunk)
+    ws = torch.empty(vg.workspace_size(h.h, S, P, prec), dtype=torch.uint8, device=dev)
+    out = torch.empty((len(OUT_LAYERS), S, P, 2 * model.dim), device=dev, dtype=torch.bfloat16)
+    # load the kernels with a one-frame call (not a step)
+    vg.aggregate(h.h, tokens[:1], layers, [0], prec, out=out[:1, :1], ws=ws)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats(dev)
+
+    for i in range(args.warmup):
+        vg.aggregate(h.h, tokens, layers, OUT_LAYERS, prec, out=out, ws=ws)
+        torch.cuda.synchronize()
+        log(f"warmup step {i} done")
+    vg.timing_enable(h.h, True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(args.steps):
+        vg.aggregate(h.h, tokens, layers, OUT_LAYERS, prec, out=out, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sec = e0.elapsed_time(e1) * 1e-3
+    tm = vg.timing_read(h.h)
+    vg.timing_enable(h.h, False)
+    peak_gb = torch.cuda.max_memory_allocated(dev) / 1e9
+    log(f"timed {args.steps} step(s): {sec:.3f}s (host wall {wall:.3f}s)")
+    ga = tm["attn_global"]
+    ga_tflops = ga["flops"] / (ga["ms"] * 1e-3) / 1e12 if ga["ms"] > 0 else None
+    avg_ms = ga["ms"] / max(1, ga["launches"])
+    flops_per_launch = ga["flops"] / max(1, ga["launches"])
+    N = S * P
+    del out, ws
+    torch.cuda.empty_cache()
+
+    extra = {}
+    if not args.no_extra:
+        gen2 = torch.Generator(device=dev)
+        gen2.manual_seed(args.seed + 1)
+        r, ms = attn_only_rate(h.h, S, vg.BF16, dev, gen2)
+        extra["bf16_S%d" % S] = {"tflops": r, "ms": ms}
+        log(f"standalone bf16 global attention S={S}: {r:.1f} TFLOP/s")
+        r, ms = attn_only_rate(h.h, min(S, 200), vg.F32, dev, gen2)
+        extra["f32_S%d" % min(S, 200)] = {"tflops": r, "ms": ms}
+        log(f"standalone f32 global attention S={min(S, 200)}: {r:.1f} TFLOP/s")
+    h.close()
+
+    res = {
+        "metric": "frames/sec + global-attn TFLOP/s at S=1000 (BF16 vs FP8 vs FP32), peak HBM GB",
+        "value": S * args.steps / sec,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp8": "fp8_e4m3+bf16", "bf16": "bf16", "f32": "f32"}[args.prec],
+        "data": "synthetic (tokens N(0,1), weights N(0,0.02), seeded, device-generated)",
+        "config": {"workload": f"vggt_l_aggregator_S{S}_P{P}_{args.prec}", "frames": S, "tokens_per_frame": P,
+                   "global_tokens": N, "dim": model.dim, "heads": model.heads, "head_dim": model.head_dim,
+                   "mlp_hidden": model.mlp_hidden, "depth": model.depth, "out_layers": list(OUT_LAYERS),
+                   "frame_chunk": model.frame_chunk, "global_attention_prec": args.prec},
+        "global_attn_tflops": ga_tflops,
+        "peak_hbm_gb": peak_gb,
+        "kernel_time_ms": {k: v["ms"] for k, v in tm.items() if isinstance(v, dict)},
+        "attn_only_tflops": extra,
+        "roofline": {
+            "kernel": f"attn_{args.prec}_kernel (global attention)",
+            "bound": "mfma",
+            "achieved": ga_tflops,
+            "peak": PEAK_TFLOPS[args.prec],
+            "unit": "TFLOP/s",
+            "frac": (ga_tflops / PEAK_TFLOPS[args.prec]) if ga_tflops else None,
+            "traffic": None,
+            "flops_per_launch": flops_per_launch,
+            "avg_launch_ms": avg_ms,
+            "launches": ga["launches"],
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample")
+        res["cpu_baseline"] = cpu_baseline(S, P)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

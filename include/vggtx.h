@@ -1,0 +1,215 @@
+/*
+ * vggtx — MI355X (gfx950) library for the memory-efficient dense-view
+ * aggregator of VGGT-X (arXiv 2509.25191, Sec. 3.2).
+ *
+ * The aggregator runs `depth` alternating-attention layers over S frames of P
+ * tokens each.  Every layer is a frame block (attention restricted to the P
+ * tokens of one frame) followed by a global block (attention over every token
+ * of the scene).  Only the outputs of the requested layers are kept, all
+ * other activations are overwritten in place (the paper's "VGGT-" change), and
+ * token-local work is processed in chunks of `frame_chunk` frames (the
+ * paper's "VGGT--" change, chunk 128 in Sec. 4.1).
+ *
+ * Block (a reading: the paper does not spell the block out): pre-LayerNorm
+ * transformer block, x += MHA(LN1(x)); x += W2 GELU(W1 LN2(x) + b1) + b2, with
+ * exact-erf GELU, biases on every Linear, packed [q | k | v] projection
+ * (head h = columns h*D .. h*D+D-1 of each part), attention scale 1/sqrt(D).
+ *
+ * Conventions for every entry point:
+ *   - All pointers named as device pointers must point to device memory of the
+ *     device the handle was created on; the caller owns every buffer (inputs,
+ *     outputs, weights, workspace).  The library never allocates device memory.
+ *   - Host pointers (offset tables, weight tables, layer lists) are read before
+ *     the call returns.
+ *   - Work is enqueued on `stream` and the call returns without waiting; device
+ *     pointers must stay valid until that work completes.
+ *   - Arguments are validated on the host before anything is enqueued: a call
+ *     that returns an error has enqueued nothing and written nothing.
+ *   - Errors never abort the process; the returned status says what failed and
+ *     vggtx_last_error() (thread-local) gives a message.
+ *   - Linear weights are stored [out, in] row-major (y = x W^T + b).
+ *   - Element types: VGGTX_F32 runs every step in float32 (weights, Q/K/V,
+ *     attention, outputs float32).  VGGTX_BF16 takes bfloat16 weights and runs
+ *     GEMMs and attention on bfloat16 operands with float32 accumulation, float32
+ *     softmax statistics and a float32 residual stream.  VGGTX_FP8_E4M3 is
+ *     VGGTX_BF16 with global attention computed on OCP FP8 E4M3 Q, K, V and
+ *     probabilities with per-128-row-block float32 scales.
+ */
+#ifndef VGGTX_H
+#define VGGTX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VGGTX_OK = 0,
+  VGGTX_E_INVALID = 1,     /* bad shape, null pointer, bad layer list, bad offsets */
+  VGGTX_E_UNSUPPORTED = 2, /* head_dim != 64, dim or mlp_hidden not a multiple of 128, not gfx950 */
+  VGGTX_E_WORKSPACE = 3,   /* workspace pointer null or smaller than required */
+  VGGTX_E_HIP = 4,         /* a HIP call failed (message in vggtx_last_error) */
+  VGGTX_E_NODEVICE = 5     /* no usable GPU / bad device ordinal */
+} vggtx_status;
+
+typedef enum { VGGTX_F32 = 0, VGGTX_BF16 = 1, VGGTX_FP8_E4M3 = 2 } vggtx_prec;
+
+/* storage type of an output buffer */
+typedef enum { VGGTX_OUT_F32 = 0, VGGTX_OUT_BF16 = 1 } vggtx_dtype;
+
+typedef struct vggtx_ctx* vggtx_handle;
+
+typedef struct {
+  int dim;          /* C; multiple of 128 */
+  int heads;        /* H; dim == heads * head_dim */
+  int head_dim;     /* D; must be 64 */
+  int mlp_hidden;   /* F; multiple of 128 */
+  float ln_eps;     /* LayerNorm epsilon (1e-6 by default) */
+  int frame_chunk;  /* frames per chunk for token-local work; results do not depend on it */
+} vggtx_config;
+
+/* Device pointers of one block's parameters: float32 for VGGTX_F32, bfloat16
+ * otherwise.  Shapes: ln*_g/ln*_b [C]; w_qkv [3C, C]; b_qkv [3C]; w_o [C, C];
+ * b_o [C]; w_fc1 [F, C]; b_fc1 [F]; w_fc2 [C, F]; b_fc2 [C]. */
+typedef struct {
+  const void *ln1_g, *ln1_b, *w_qkv, *b_qkv, *w_o, *b_o;
+  const void *ln2_g, *ln2_b, *w_fc1, *b_fc1, *w_fc2, *b_fc2;
+} vggtx_block_w;
+
+/* One alternating-attention layer: frame block, then global block. */
+typedef struct {
+  vggtx_block_w frame;
+  vggtx_block_w global;
+} vggtx_pair_w;
+
+/* Row layout of a [tokens, heads, head_dim] tensor: element (n, h, d) lives at
+ * base + n * token_stride + h * head_stride + d (in elements). */
+typedef struct {
+  int64_t token_stride;
+  int64_t head_stride;
+} vggtx_layout;
+
+/* Create a handle on `device` for model shape `cfg` (copied).  Fails with
+ * VGGTX_E_NODEVICE when the device does not exist and VGGTX_E_UNSUPPORTED when
+ * it is not gfx950 or the shape is outside what the kernels support. */
+vggtx_status vggtx_create(vggtx_handle* h, int device, const vggtx_config* cfg);
+vggtx_status vggtx_destroy(vggtx_handle h);
+
+/* Workspace bytes that vggtx_aggregate / vggtx_aggregate_varlen / vggtx_block
+ * need for `total_frames` frames of P tokens at precision `prec`. */
+vggtx_status vggtx_workspace_size(vggtx_handle h, int total_frames, int P, vggtx_prec prec, size_t* bytes);
+
+/* Aggregator forward over one scene (Sec. 3.2).
+ *   tokens     device, float32 [S, P, C] (read only)
+ *   w          host array[depth] of per-layer weight pointers
+ *   out_layers host int32 [n_out], strictly increasing, each in [0, depth)
+ *   out        device [n_out, S, P, 2C] of `out_dtype`: out[i, s, p, 0:C] is the
+ *              frame-block output and out[i, s, p, C:2C] the global-block output
+ *              of layer out_layers[i]
+ *   ws         device workspace of at least vggtx_workspace_size bytes
+ * Layers after the last requested one are not run. */
+vggtx_status vggtx_aggregate(vggtx_handle h, const float* tokens, int S, int P,
+                             const vggtx_pair_w* w, int depth,
+                             const int32_t* out_layers, int n_out,
+                             void* out, vggtx_dtype out_dtype, vggtx_prec prec,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Same over several independent scenes stored back to back: frames of scene i
+ * are frame_offsets[i] .. frame_offsets[i+1]-1 (host int32 [n_scenes+1],
+ * frame_offsets[0] == 0, non-decreasing; an empty scene contributes nothing).  Global attention of a token is
+ * restricted to the tokens of its own scene; all scenes run in the same
+ * launches. */
+vggtx_status vggtx_aggregate_varlen(vggtx_handle h, const float* tokens,
+                                    const int32_t* frame_offsets, int n_scenes, int P,
+                                    const vggtx_pair_w* w, int depth,
+                                    const int32_t* out_layers, int n_out,
+                                    void* out, vggtx_dtype out_dtype, vggtx_prec prec,
+                                    void* ws, size_t ws_bytes, void* stream);
+
+/* One transformer block (the unit both halves of a layer are made of) over
+ * `n_seq` sequences back to back; token offsets host int32 [n_seq+1]
+ * (non-decreasing, offsets[0] == 0).  Attention of a token is restricted to its
+ * own sequence.  x_in and x_out are device float32 [n_tokens, C] and may be the
+ * same buffer.  The workspace must hold vggtx_workspace_size(h, n_seq,
+ * longest sequence, prec) bytes. */
+vggtx_status vggtx_block(vggtx_handle h, const float* x_in, float* x_out,
+                         const int32_t* seq_offsets, int n_seq,
+                         const vggtx_block_w* w, vggtx_prec prec,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes that vggtx_attn_global needs for the sequences
+ * seq_offsets[0..n_seq] (host int32, token offsets) of H heads of dimension D
+ * at precision `prec`; for vggtx_attn_frame pass the frame offsets f * P. */
+vggtx_status vggtx_attn_workspace_size(vggtx_handle h, const int32_t* seq_offsets, int n_seq, int H, int D,
+                                       vggtx_prec prec, size_t* bytes);
+
+/* Frame attention (Sec. 3.2: attention restricted to the P tokens of each of S
+ * frames): o = softmax(q k^T / sqrt(D)) v per frame and head.
+ *   q, k, v  device [S*P, H, D] with layout `in_layout`: bfloat16 for
+ *            VGGTX_BF16, float32 for VGGTX_F32 (VGGTX_FP8_E4M3 is not offered
+ *            for frame attention)
+ *   o        device, same element type, layout `out_layout`. */
+vggtx_status vggtx_attn_frame(vggtx_handle h, const void* q, const void* k, const void* v, void* o,
+                              int S, int P, int H, int D,
+                              vggtx_layout in_layout, vggtx_layout out_layout, vggtx_prec prec,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* Global attention (Sec. 3.2: attention over all tokens of a scene), streamed:
+ * no score matrix is stored.  Sequence i covers tokens seq_offsets[i] ..
+ * seq_offsets[i+1]-1 (host int32 [n_seq+1], seq_offsets[0] == 0, non-
+ * decreasing; empty sequences are skipped).  q, k, v: bfloat16 for VGGTX_BF16 and VGGTX_FP8_E4M3 (the
+ * library quantises them into the workspace), float32 for VGGTX_F32; o has
+ * the same element type as q. */
+vggtx_status vggtx_attn_global(vggtx_handle h, const void* q, const void* k, const void* v, void* o,
+                               const int32_t* seq_offsets, int n_seq, int H, int D,
+                               vggtx_layout in_layout, vggtx_layout out_layout, vggtx_prec prec,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* FP8 E4M3 quantiser used by the FP8 global attention.  x: device bfloat16
+ * [n_tokens, H, D] with layout `in_layout`.  For every head and every
+ * 128-token block of every sequence (blocks start at each sequence start; the
+ * last block of a sequence may be shorter): s = amax / 448 (1 when amax == 0)
+ * and codes = RNE-saturate(x * (448 / amax)) in float32.
+ *   codes  device uint8 [H, n_tokens, D]
+ *   scales device float32 [H, n_blocks], n_blocks = sum_i ceil(len_i / 128),
+ *          blocks numbered sequence by sequence. */
+vggtx_status vggtx_quantize_fp8(vggtx_handle h, const void* x, vggtx_layout in_layout,
+                                const int32_t* seq_offsets, int n_seq, int H, int D,
+                                uint8_t* codes, float* scales, void* stream);
+
+/* Kernel timing (tracing).  While enabled, every kernel launch of the classes
+ * below is bracketed by a pair of HIP events recorded on its launch stream, and
+ * vggtx_timing_read() waits for those events and returns, per class, the summed
+ * elapsed time, the number of launches and the algorithmic work of those
+ * launches (attention: 4 * D * H * sum of sequence length squared flops; GEMMs:
+ * 2 * M * N * K flops).  At most 4096 launches are recorded between reads;
+ * later ones are counted in `dropped`.  Enabling or reading clears the record.
+ * The events are host-side objects of the handle; no device memory is
+ * allocated. */
+typedef enum {
+  VGGTX_K_ATTN_GLOBAL = 0, /* global attention (any precision) */
+  VGGTX_K_ATTN_FRAME = 1,  /* frame attention */
+  VGGTX_K_GEMM = 2,        /* projection / MLP GEMMs with their fused epilogues */
+  VGGTX_K_OTHER = 3,       /* LayerNorm, V transposition, FP8 quantisation, copies */
+  VGGTX_K_COUNT = 4
+} vggtx_kernel_class;
+
+typedef struct {
+  double total_ms;
+  int64_t launches;
+  double flops;
+} vggtx_timing;
+
+vggtx_status vggtx_timing_enable(vggtx_handle h, int enable);
+vggtx_status vggtx_timing_read(vggtx_handle h, vggtx_timing out[VGGTX_K_COUNT], int64_t* dropped);
+
+const char* vggtx_status_str(vggtx_status s);
+/* Message of the last failing call on this thread ("" if none). */
+const char* vggtx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VGGTX_H */

@@ -1,0 +1,649 @@
+// Streamed ("flash") attention for the frame and global blocks of the
+// aggregator (arXiv 2509.25191, Sec. 3.2), plus the V transposition and the
+// FP8 E4M3 quantiser that feed it.
+//
+// Every kernel computes, per sequence and head, O = softmax(Q K^T / sqrt(D)) V
+// without storing the score matrix: keys are visited in tiles, a running row
+// maximum m and row sum l are kept in float32 and the partial output is
+// rescaled by 2^((m_old - m_new) * log2(e)/sqrt(D)) whenever m grows.
+//
+// Work decomposition: one workgroup (4 waves) per (query tile, head).  The
+// query tile of a wave is 32*QB rows; scores are computed transposed,
+// S^T = K Q^T, so that every lane owns one query column of the MFMA
+// accumulator.  That makes the softmax statistics lane-local (plus one
+// exchange with lane l^32) and lets the probabilities feed the P V product
+// (O^T = V^T P^T) straight from registers.
+#include "common.h"
+#include "kernels.h"
+
+namespace vggtx {
+
+struct Item {
+  int q0, s0, s1, vb, bb;
+};
+
+// Map a work-item index to its query tile and sequence.
+__device__ __forceinline__ Item resolve_item(const SeqTable& t, int item, int rows_per_item) {
+  Item it;
+  if (t.uniform) {
+    const int seq = item / t.tiles_per_seq;
+    const int tt = item - seq * t.tiles_per_seq;
+    it.s0 = t.start[0] + seq * t.len;
+    it.s1 = it.s0 + t.len;
+    it.vb = t.vt_base[0] + seq * ((t.len + kKeyPad - 1) / kKeyPad * kKeyPad);
+    it.bb = t.blk_base[0] + seq * ((t.len + kQuantRows - 1) / kQuantRows);
+    it.q0 = it.s0 + tt * rows_per_item;
+  } else {
+    int seq = 0;
+    while (seq < t.n_seq - 1 && item >= t.tile_end[seq]) ++seq;
+    const int prev = seq ? t.tile_end[seq - 1] : 0;
+    it.s0 = t.start[seq];
+    it.s1 = t.end[seq];
+    it.vb = t.vt_base[seq];
+    it.bb = t.blk_base[seq];
+    it.q0 = it.s0 + (item - prev) * rows_per_item;
+  }
+  return it;
+}
+
+// ============================================================== BF16 kernel
+//
+// LDS tiles (BN = 64 keys, D = 64), 16-byte granules XOR-swizzled with the row
+// index to keep ds_read_b128 conflict free:
+//   Ks[key][d]      granule (d/8) ^ (key & 7)
+//   Vs[d][key']     transposed V; inside every 16-key group the keys are
+//                   stored in the order in which a lane's MFMA k-slots need
+//                   them (slot j of lane group g <-> key 8*(j/4) + 4*g + j%4),
+//                   granule ^ (d & 7).
+template <int QB, bool OUT_F32>
+__global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
+  constexpr int BN = 64, D = kHeadDim, BM = 128 * QB;
+  __shared__ __attribute__((aligned(16))) bf16 Ks[2][BN * D];
+  __shared__ __attribute__((aligned(16))) bf16 Vs[2][D * BN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 5, r32 = lane & 31;
+  const int head = blockIdx.y;
+  const Item it = resolve_item(p.seqs, blockIdx.x, BM);
+
+  const bf16* Q = (const bf16*)p.q + head * p.q_hs;
+  const bf16* K = (const bf16*)p.k + head * p.k_hs;
+  const bf16* Vt = (const bf16*)p.vt + head * p.vt_hs + it.vb;
+
+  const bf16x8 zero8 = {};
+  bf16x8 qf[QB][4];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const int row = it.q0 + (wave * QB + qb) * 32 + r32;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      qf[qb][c] = row < it.s1 ? *(const bf16x8*)(Q + row * p.q_ts + 16 * c + 8 * g) : zero8;
+  }
+
+  bf16x8 kreg[2], vreg[2];
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = (tid >> 3) + 32 * i, ch = tid & 7;
+      const int key = kt + r;
+      kreg[i] = key < it.s1 ? *(const bf16x8*)(K + key * p.k_ts + ch * 8) : zero8;
+      vreg[i] = *(const bf16x8*)(Vt + r * p.vt_ds + (kt - it.s0) + ch * 8);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int r = (tid >> 3) + 32 * i, ch = tid & 7;
+      *(bf16x8*)&Ks[buf][r * D + ((ch ^ (r & 7)) * 8)] = kreg[i];
+      const int hp = ch >> 1, a = ch & 1;
+      const bf16x4 lo = {vreg[i][0], vreg[i][1], vreg[i][2], vreg[i][3]};
+      const bf16x4 hi = {vreg[i][4], vreg[i][5], vreg[i][6], vreg[i][7]};
+      *(bf16x4*)&Vs[buf][r * BN + (((2 * hp) ^ (r & 7)) * 8) + 4 * a] = lo;
+      *(bf16x4*)&Vs[buf][r * BN + (((2 * hp + 1) ^ (r & 7)) * 8) + 4 * a] = hi;
+    }
+  };
+
+  f32x16 oacc[QB][2];
+  float m_run[QB], l_run[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    oacc[qb][0] = f32x16{};
+    oacc[qb][1] = f32x16{};
+    m_run[qb] = -INFINITY;
+    l_run[qb] = 0.f;
+  }
+  const float c2 = p.scale_log2;
+  const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
+
+  gload(it.s0);
+  lstore(0);
+  __syncthreads();
+
+  for (int t = 0; t < ntiles; ++t) {
+    const int kt = it.s0 + t * BN, buf = t & 1;
+    if (t + 1 < ntiles) gload(kt + BN);
+
+    bf16x8 kf[2][4], vf[2][2][2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int r = kb * 32 + r32;
+        kf[kb][c] = *(const bf16x8*)&Ks[buf][r * D + (((2 * c + g) ^ (r & 7)) * 8)];
+      }
+#pragma unroll
+    for (int db = 0; db < 2; ++db)
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int d = db * 32 + r32;
+          vf[db][kb][h] = *(const bf16x8*)&Vs[buf][d * BN + (((2 * (2 * kb + h) + g) ^ (d & 7)) * 8)];
+        }
+
+    const bool tail = kt + BN > it.s1;
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      f32x16 s[2];
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+        s[kb] = f32x16{};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[kb] = mfma_bf16(kf[kb][c], qf[qb][c], s[kb]);
+      }
+      if (tail) {
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int key = kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3);
+            if (key >= it.s1) s[kb][i] = -INFINITY;
+          }
+      }
+      float mx = s[0][0];
+#pragma unroll
+      for (int i = 1; i < 16; ++i) mx = __builtin_fmaxf(mx, s[0][i]);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) mx = __builtin_fmaxf(mx, s[1][i]);
+      mx = __builtin_fmaxf(mx, __shfl_xor(mx, 32));
+      const float m_new = __builtin_fmaxf(m_run[qb], mx);
+      if (__any(m_new > m_run[qb])) {
+        const float alpha = fast_exp2((m_run[qb] - m_new) * c2);
+        l_run[qb] *= alpha;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          oacc[qb][0][i] *= alpha;
+          oacc[qb][1][i] *= alpha;
+        }
+        m_run[qb] = m_new;
+      }
+      const float mc = m_new * c2;
+      bf16x8 pb[2][2];
+      float ls = 0.f;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const float e = fast_exp2(__builtin_fmaf(s[kb][i], c2, -mc));
+          ls += e;
+          pb[kb][i >> 3][i & 7] = f2bf(e);
+        }
+      l_run[qb] += ls;
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) oacc[qb][db] = mfma_bf16(vf[db][kb][h], pb[kb][h], oacc[qb][db]);
+    }
+
+    if (t + 1 < ntiles) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const float lt = l_run[qb] + __shfl_xor(l_run[qb], 32);
+    const float inv = 1.f / lt;
+    const int row = it.q0 + (wave * QB + qb) * 32 + r32;
+    if (row < it.s1) {
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int i = 0; i < 16; i += 4) {
+          const int d = db * 32 + 8 * (i >> 2) + 4 * g;
+          if (OUT_F32) {
+            float* o = (float*)p.o + row * p.o_ts + head * p.o_hs + d;
+            const f32x4 v = {oacc[qb][db][i] * inv, oacc[qb][db][i + 1] * inv, oacc[qb][db][i + 2] * inv,
+                             oacc[qb][db][i + 3] * inv};
+            *(f32x4*)o = v;
+          } else {
+            bf16* o = (bf16*)p.o + row * p.o_ts + head * p.o_hs + d;
+            const bf16x4 v = {f2bf(oacc[qb][db][i] * inv), f2bf(oacc[qb][db][i + 1] * inv),
+                              f2bf(oacc[qb][db][i + 2] * inv), f2bf(oacc[qb][db][i + 3] * inv)};
+            *(bf16x4*)o = v;
+          }
+        }
+    }
+  }
+}
+
+// ============================================================== FP32 kernel
+// Same structure on the float32 MFMA (32x32x2): 32 queries per wave, BN = 32
+// keys per tile, K and V key-major in LDS with padded rows.
+__global__ __launch_bounds__(256, 1) void attn_f32_kernel(AttnParams p) {
+  constexpr int BN = 32, D = kHeadDim, BM = 128;
+  __shared__ float Ks[2][BN][D + 1];
+  __shared__ float Vs[2][BN][D + 4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 5, r32 = lane & 31;
+  const int head = blockIdx.y;
+  const Item it = resolve_item(p.seqs, blockIdx.x, BM);
+  const float* Q = (const float*)p.q + head * p.q_hs;
+  const float* K = (const float*)p.k + head * p.k_hs;
+  const float* V = (const float*)p.v + head * p.v_hs;
+
+  float qf[32];
+  const int qrow = it.q0 + wave * 32 + r32;
+#pragma unroll
+  for (int c = 0; c < 32; ++c) qf[c] = qrow < it.s1 ? Q[qrow * p.q_ts + 2 * c + g] : 0.f;
+
+  f32x4 kreg[2], vreg[2];
+  const int lr = tid >> 3, ld0 = (tid & 7) * 8;
+  auto gload = [&](int kt) {
+    const int key = kt + lr;
+    const f32x4 z = {};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      kreg[i] = key < it.s1 ? *(const f32x4*)(K + key * p.k_ts + ld0 + 4 * i) : z;
+      vreg[i] = key < it.s1 ? *(const f32x4*)(V + key * p.v_ts + ld0 + 4 * i) : z;
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        Ks[buf][lr][ld0 + 4 * i + j] = kreg[i][j];
+        Vs[buf][lr][ld0 + 4 * i + j] = vreg[i][j];
+      }
+  };
+
+  f32x16 oacc[2] = {f32x16{}, f32x16{}};
+  float m_run = -INFINITY, l_run = 0.f;
+  const float c2 = p.scale_log2;
+  const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
+  gload(it.s0);
+  lstore(0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    const int kt = it.s0 + t * BN, buf = t & 1;
+    if (t + 1 < ntiles) gload(kt + BN);
+    f32x16 s = {};
+#pragma unroll
+    for (int c = 0; c < 32; ++c) s = mfma_f32(Ks[buf][r32][2 * c + g], qf[c], s);
+    if (kt + BN > it.s1) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (kt + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) s[i] = -INFINITY;
+    }
+    float mx = s[0];
+#pragma unroll
+    for (int i = 1; i < 16; ++i) mx = __builtin_fmaxf(mx, s[i]);
+    mx = __builtin_fmaxf(mx, __shfl_xor(mx, 32));
+    const float m_new = __builtin_fmaxf(m_run, mx);
+    const float alpha = fast_exp2((m_run - m_new) * c2);
+    m_run = m_new;
+    l_run *= alpha;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      oacc[0][i] *= alpha;
+      oacc[1][i] *= alpha;
+    }
+    const float mc = m_new * c2;
+    float pv[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      pv[i] = fast_exp2(__builtin_fmaf(s[i], c2, -mc));
+      l_run += pv[i];
+    }
+#pragma unroll
+    for (int db = 0; db < 2; ++db)
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const int key = 8 * (c >> 2) + 4 * g + (c & 3);
+        oacc[db] = mfma_f32(Vs[buf][key][db * 32 + r32], pv[c], oacc[db]);
+      }
+    if (t + 1 < ntiles) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  const float lt = l_run + __shfl_xor(l_run, 32);
+  const float inv = 1.f / lt;
+  if (qrow < it.s1) {
+#pragma unroll
+    for (int db = 0; db < 2; ++db)
+#pragma unroll
+      for (int i = 0; i < 16; i += 4) {
+        const int d = db * 32 + 8 * (i >> 2) + 4 * g;
+        float* o = (float*)p.o + qrow * p.o_ts + head * p.o_hs + d;
+        const f32x4 v = {oacc[db][i] * inv, oacc[db][i + 1] * inv, oacc[db][i + 2] * inv, oacc[db][i + 3] * inv};
+        *(f32x4*)o = v;
+      }
+  }
+}
+
+
+// ============================================================== FP8 kernel
+// Global attention on OCP E4M3 operands (MFMA 32x32x64 f8f6f4, one MFMA per
+// 32x32 score block since K = D = 64).  Q, K and V carry one float32 scale
+// per 128-row block of their sequence; the K-block and Q-block scales and
+// log2(e)/sqrt(D) multiply the raw score in the exponent's FMA.  The V-block
+// scale is folded into the probabilities before they are rounded to E4M3:
+// A_j = p_j * 448 * s_v(block(j)) / vmax, where vmax is the largest V scale of
+// the head, so that one PV accumulator serves every key block and
+// O = (vmax / 448) * sum_j A_j V8_j / sum_j p_j.
+//
+// The row sum l is taken from the same rounded A8 values that feed the PV
+// product (one extra MFMA against an all-ones operand), so the output stays
+// a convex combination of value rows whatever the rounding of P.
+//
+// LDS: Ks[key][d] bytes, 16-byte granules swizzled with (key >> 1) & 3;
+//      Vs[d][key'] bytes, keys of every 32-key block permuted so that lane
+//      group g finds its 16 k-slots in one granule (slot j of group g <->
+//      key 32*(j/16) + 8*((j%16)/4) + 4*g + j%4), granules swizzled with
+//      (d >> 1) & 3.
+__global__ __launch_bounds__(256, 2) void attn_fp8_kernel(AttnParams p) {
+  constexpr int BN = 64, D = kHeadDim, BM = 128;
+  __shared__ __attribute__((aligned(16))) uint8_t Ks[2][BN * D];
+  __shared__ __attribute__((aligned(16))) uint8_t Vs[2][D * BN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 5, r32 = lane & 31;
+  const int head = blockIdx.y;
+  const Item it = resolve_item(p.seqs, blockIdx.x, BM);
+  const uint8_t* Q = (const uint8_t*)p.q + head * p.q_hs;
+  const uint8_t* K = (const uint8_t*)p.k + head * p.k_hs;
+  const uint8_t* Vt = (const uint8_t*)p.vt + head * p.vt_hs + it.vb;
+  const float* SQ = p.sq + head * p.sc_hs + it.bb;
+  const float* SK = p.sk + head * p.sc_hs + it.bb;
+  const float* SV = p.sv + head * p.sc_hs + it.bb;
+  const float vmax = p.vmax[head];
+
+  const int qrow = it.q0 + wave * 32 + r32;
+  const i32x8 zero8 = {};
+  const int one4 = 0x38383838;  // four E4M3 1.0 codes
+  const i32x8 ones8 = {one4, one4, one4, one4, one4, one4, one4, one4};
+  const i32x8 qf = qrow < it.s1 ? *(const i32x8*)(Q + qrow * p.q_ts + 32 * g) : zero8;
+  const float sq = SQ[(it.q0 - it.s0) / kQuantRows];
+
+  i32x4 kreg, vreg;
+  const int lr = tid >> 2, lch = tid & 3;
+  auto gload = [&](int kt) {
+    const i32x4 z = {};
+    const int key = kt + lr;
+    kreg = key < it.s1 ? *(const i32x4*)(K + key * p.k_ts + lch * 16) : z;
+    vreg = *(const i32x4*)(Vt + lr * p.vt_ds + (kt - it.s0) + lch * 16);
+  };
+  auto lstore = [&](int buf) {
+    *(i32x4*)&Ks[buf][lr * D + ((lch ^ ((lr >> 1) & 3)) * 16)] = kreg;
+    const int kb = lch >> 1, h = lch & 1, sw = (lr >> 1) & 3;
+    const i32x2 a = {vreg[0], vreg[2]}, b = {vreg[1], vreg[3]};
+    *(i32x2*)&Vs[buf][lr * BN + (((2 * kb) ^ sw) * 16) + 8 * h] = a;
+    *(i32x2*)&Vs[buf][lr * BN + (((2 * kb + 1) ^ sw) * 16) + 8 * h] = b;
+  };
+
+  f32x16 oacc[2] = {f32x16{}, f32x16{}};
+  float m_run = -INFINITY, l_run = 0.f;
+  const float c2 = p.scale_log2;
+  const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
+  gload(it.s0);
+  lstore(0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; ++t) {
+    const int kt = it.s0 + t * BN, buf = t & 1;
+    if (t + 1 < ntiles) gload(kt + BN);
+    i32x8 kf[2], vf[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const int r = kb * 32 + r32, sw = (r >> 1) & 3;
+      const i32x4 lo = *(const i32x4*)&Ks[buf][r * D + (((2 * g) ^ sw) * 16)];
+      const i32x4 hi = *(const i32x4*)&Ks[buf][r * D + (((2 * g + 1) ^ sw) * 16)];
+      kf[kb] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
+#pragma unroll
+    for (int db = 0; db < 2; ++db) {
+      const int d = db * 32 + r32, sw = (d >> 1) & 3;
+      const i32x4 lo = *(const i32x4*)&Vs[buf][d * BN + ((g ^ sw) * 16)];
+      const i32x4 hi = *(const i32x4*)&Vs[buf][d * BN + (((2 + g) ^ sw) * 16)];
+      vf[db] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    }
+    f32x16 s[2];
+    s[0] = mfma_fp8(kf[0], qf, f32x16{});
+    s[1] = mfma_fp8(kf[1], qf, f32x16{});
+    const int blk = (kt - it.s0) / kQuantRows;
+    const float sigma = sq * SK[blk] * c2;
+    const float rb = 448.f * SV[blk] / vmax;
+    if (kt + BN > it.s1) {
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) s[kb][i] = -INFINITY;
+    }
+    float mx = s[0][0];
+#pragma unroll
+    for (int i = 1; i < 16; ++i) mx = __builtin_fmaxf(mx, s[0][i]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) mx = __builtin_fmaxf(mx, s[1][i]);
+    mx = __builtin_fmaxf(mx, __shfl_xor(mx, 32));
+    const float m_new = __builtin_fmaxf(m_run, mx * sigma);
+    if (__any(m_new > m_run)) {
+      const float alpha = fast_exp2(m_run - m_new);
+      l_run *= alpha;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        oacc[0][i] *= alpha;
+        oacc[1][i] *= alpha;
+      }
+      m_run = m_new;
+    }
+    const float off = m_new - __builtin_amdgcn_logf(rb);
+    i32x8 pw;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int i = 0; i < 16; i += 4) {
+        const float e0 = fast_exp2(__builtin_fmaf(s[kb][i], sigma, -off));
+        const float e1 = fast_exp2(__builtin_fmaf(s[kb][i + 1], sigma, -off));
+        const float e2 = fast_exp2(__builtin_fmaf(s[kb][i + 2], sigma, -off));
+        const float e3 = fast_exp2(__builtin_fmaf(s[kb][i + 3], sigma, -off));
+        pw[(16 * kb + i) >> 2] = (int)(cvt_e4m3x2(e0, e1) | (cvt_e4m3x2(e2, e3) << 16));
+      }
+    const f32x16 lsum = mfma_fp8(ones8, pw, f32x16{});
+    l_run = __builtin_fmaf(lsum[0], 1.f / rb, l_run);
+    oacc[0] = mfma_fp8(vf[0], pw, oacc[0]);
+    oacc[1] = mfma_fp8(vf[1], pw, oacc[1]);
+    if (t + 1 < ntiles) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  const float inv = vmax / 448.f / l_run;
+  if (qrow < it.s1) {
+#pragma unroll
+    for (int db = 0; db < 2; ++db)
+#pragma unroll
+      for (int i = 0; i < 16; i += 4) {
+        const int d = db * 32 + 8 * (i >> 2) + 4 * g;
+        bf16* o = (bf16*)p.o + qrow * p.o_ts + head * p.o_hs + d;
+        const bf16x4 v = {f2bf(oacc[db][i] * inv), f2bf(oacc[db][i + 1] * inv), f2bf(oacc[db][i + 2] * inv),
+                          f2bf(oacc[db][i + 3] * inv)};
+        *(bf16x4*)o = v;
+      }
+  }
+}
+
+// ============================================================== V transpose
+// One workgroup per (64-token tile, head): v [tokens, H, D] -> vt[h][d][col]
+// with every sequence starting at a multiple of 64 columns; columns past the
+// end of a sequence are written as zeros.
+__global__ __launch_bounds__(256) void v_transpose_bf16_kernel(const bf16* v, int64_t v_ts, int64_t v_hs, bf16* vt,
+                                                               int64_t vt_hs, int64_t vt_ds, SeqTable seqs) {
+  __shared__ bf16 T[64][64 + 2];
+  const int tid = threadIdx.x, head = blockIdx.y;
+  const Item it = resolve_item(seqs, blockIdx.x, 64);
+  const bf16* V = v + head * v_hs;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int r = (tid >> 3) + 32 * i, ch = tid & 7;
+    const int row = it.q0 + r;
+    bf16x8 x = {};
+    if (row < it.s1) x = *(const bf16x8*)(V + row * v_ts + ch * 8);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) T[r][ch * 8 + j] = x[j];
+  }
+  __syncthreads();
+  bf16* out = vt + head * vt_hs + it.vb + (it.q0 - it.s0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int d = (tid >> 3) + 32 * i, ch = tid & 7;
+    bf16x8 y;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) y[j] = T[ch * 8 + j][d];
+    *(bf16x8*)(out + d * vt_ds + ch * 8) = y;
+  }
+}
+
+// ============================================================== FP8 quantiser
+// One workgroup per (128-row scale block, head).  amax over the block's rows
+// and all D columns; s = amax / 448; codes = E4M3(x * (448 / amax)).
+__global__ __launch_bounds__(256) void quant_fp8_kernel(const bf16* x, int64_t x_ts, int64_t x_hs, uint8_t* codes,
+                                                        int64_t c_hs, int64_t c_ds, int transposed, float* scales,
+                                                        int64_t sc_hs, SeqTable seqs) {
+  __shared__ float red[4];
+  __shared__ uint8_t T[64][128 + 4];
+  const int tid = threadIdx.x, head = blockIdx.y;
+  const Item it = resolve_item(seqs, blockIdx.x, kQuantRows);
+  const int blk = it.bb + (it.q0 - it.s0) / kQuantRows;
+  const bf16* X = x + head * x_hs;
+  const int r = tid >> 1, half = tid & 1;
+  const int row = it.q0 + r;
+  float v[32];
+  const bool valid = row < it.s1;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    bf16x8 t = {};
+    if (valid) t = *(const bf16x8*)(X + row * x_ts + half * 32 + 8 * c);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[8 * c + j] = bf2f(t[j]);
+  }
+  float amax = 0.f;
+#pragma unroll
+  for (int j = 0; j < 32; ++j) amax = __builtin_fmaxf(amax, __builtin_fabsf(v[j]));
+  amax = wave_max(amax);
+  if ((tid & 63) == 0) red[tid >> 6] = amax;
+  __syncthreads();
+  amax = __builtin_fmaxf(__builtin_fmaxf(red[0], red[1]), __builtin_fmaxf(red[2], red[3]));
+  const float inv = amax > 0.f ? 448.f / amax : 1.f;
+  if (tid == 0) scales[head * sc_hs + blk] = amax > 0.f ? amax / 448.f : 1.f;
+  uint32_t w[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    w[j] = cvt_e4m3x2(v[4 * j] * inv, v[4 * j + 1] * inv) | (cvt_e4m3x2(v[4 * j + 2] * inv, v[4 * j + 3] * inv) << 16);
+  if (!transposed) {
+    if (valid) {
+      uint8_t* o = codes + head * c_hs + (int64_t)row * kHeadDim + half * 32;
+      const i32x4 a = {(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+      const i32x4 b = {(int)w[4], (int)w[5], (int)w[6], (int)w[7]};
+      *(i32x4*)o = a;
+      *(i32x4*)(o + 16) = b;
+    }
+    return;
+  }
+  // transposed: stage [d][row] in LDS, then write padded rows of codes
+#pragma unroll
+  for (int j = 0; j < 32; ++j) T[half * 32 + j][r] = (uint8_t)((w[j >> 2] >> (8 * (j & 3))) & 0xff);
+  __syncthreads();
+  const int len = it.s1 - it.s0;
+  const int padlen = (len + kKeyPad - 1) / kKeyPad * kKeyPad;
+  const int c0 = it.q0 - it.s0;
+  const int ncols = min(kQuantRows, padlen - c0);  // 64 or 128
+  uint8_t* o = codes + head * c_hs + it.vb + c0;
+  // 64 rows (d) x ncols bytes; each thread writes 16-byte pieces
+  const int pieces = ncols / 16;
+  for (int idx = tid; idx < 64 * pieces; idx += 256) {
+    const int d = idx / pieces, pc = idx % pieces;
+    uint32_t q4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t word = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int col = pc * 16 + 4 * k + b;
+        const uint8_t cv = (c0 + col < len) ? T[d][col] : (uint8_t)0;
+        word |= (uint32_t)cv << (8 * b);
+      }
+      q4[k] = word;
+    }
+    const i32x4 a = {(int)q4[0], (int)q4[1], (int)q4[2], (int)q4[3]};
+    *(i32x4*)(o + d * c_ds + pc * 16) = a;
+  }
+}
+
+__global__ void scale_max_kernel(const float* scales, int64_t sc_hs, int n_blocks, float* vmax) {
+  const int head = blockIdx.x;
+  float m = 0.f;
+  for (int i = threadIdx.x; i < n_blocks; i += 64) m = __builtin_fmaxf(m, scales[head * sc_hs + i]);
+  m = wave_max(m);
+  if (threadIdx.x == 0) vmax[head] = m;
+}
+
+// ============================================================== launchers
+int attn_block_rows(int prec, int qb_per_wave) {
+  if (prec == 0) return 128;
+  if (prec == 2) return 128;
+  return 128 * qb_per_wave;
+}
+
+hipError_t launch_attn_bf16(const AttnParams& p, int H, int qb, bool out_f32, hipStream_t s) {
+  dim3 grid(p.n_items, H), block(256);
+  if (qb == 1) {
+    if (out_f32) hipLaunchKernelGGL((attn_bf16_kernel<1, true>), grid, block, 0, s, p);
+    else hipLaunchKernelGGL((attn_bf16_kernel<1, false>), grid, block, 0, s, p);
+  } else {
+    if (out_f32) hipLaunchKernelGGL((attn_bf16_kernel<2, true>), grid, block, 0, s, p);
+    else hipLaunchKernelGGL((attn_bf16_kernel<2, false>), grid, block, 0, s, p);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_attn_f32(const AttnParams& p, int H, hipStream_t s) {
+  hipLaunchKernelGGL(attn_f32_kernel, dim3(p.n_items, H), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_attn_fp8(const AttnParams& p, int H, hipStream_t s) {
+  hipLaunchKernelGGL(attn_fp8_kernel, dim3(p.n_items, H), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_v_transpose_bf16(const bf16* v, int64_t v_ts, int64_t v_hs, bf16* vt, int64_t vt_hs, int64_t vt_ds,
+                                   const SeqTable& seqs, int n_tiles, int H, hipStream_t s) {
+  hipLaunchKernelGGL(v_transpose_bf16_kernel, dim3(n_tiles, H), dim3(256), 0, s, v, v_ts, v_hs, vt, vt_hs, vt_ds,
+                     seqs);
+  return hipGetLastError();
+}
+
+hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, uint8_t* codes, int64_t c_hs, int64_t c_ds,
+                            bool transposed, float* scales, int64_t sc_hs, const SeqTable& seqs, int n_blocks, int H,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(quant_fp8_kernel, dim3(n_blocks, H), dim3(256), 0, s, x, x_ts, x_hs, codes, c_hs, c_ds,
+                     transposed ? 1 : 0, scales, sc_hs, seqs);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_max(const float* scales, int64_t sc_hs, int n_blocks, float* vmax, int H, hipStream_t s) {
+  hipLaunchKernelGGL(scale_max_kernel, dim3(H), dim3(64), 0, s, scales, sc_hs, n_blocks, vmax);
+  return hipGetLastError();
+}
+
+}  // namespace vggtx

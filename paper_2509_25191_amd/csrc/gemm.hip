@@ -1,0 +1,209 @@
+// Projection GEMMs of the transformer blocks with fused epilogues:
+//   EPI_QKV   [q | k | v] = h W_qkv^T + b, written head-major [H, tokens, D]
+//   EPI_RESID x += y W^T + b in place (attention out-projection and second MLP
+//             Linear), optionally copying the new residual into an output slot
+//   EPI_GELU  hidden = GELU(h W_1^T + b_1) with the exact-erf GELU
+// C[M, N] = A[M, K] W[N, K]^T: both operands are K-contiguous ("NT"), which is
+// the natural operand order of the MFMA (8 consecutive k per lane).
+#include "common.h"
+#include "kernels.h"
+
+namespace vggtx {
+
+__device__ __forceinline__ float gelu_erf(float u) { return 0.5f * u * (1.f + erff(u * 0.70710678118654752f)); }
+
+template <typename T> __device__ __forceinline__ void st4(T* p, const float v[4]);
+template <> __device__ __forceinline__ void st4<float>(float* p, const float v[4]) {
+  const f32x4 x = {v[0], v[1], v[2], v[3]};
+  *(f32x4*)p = x;
+}
+template <> __device__ __forceinline__ void st4<bf16>(bf16* p, const float v[4]) {
+  const bf16x4 x = {f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+  *(bf16x4*)p = x;
+}
+
+// Epilogue of 4 consecutive output columns of local row r (A's row r).
+// T: element type of the bias and of the q/k/v or hidden outputs.
+template <int EPI, typename T>
+__device__ __forceinline__ void epi4(const GemmParams& p, int r, int col, float v[4]) {
+  const T* bias = (const T*)p.bias;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] += ldf(bias + col + j);
+  const int64_t grow = (int64_t)p.row0 + r;
+  if (EPI == EPI_QKV) {
+    const int part = col / p.C, cc = col - part * p.C;
+    const int hh = cc / kHeadDim, d = cc - hh * kHeadDim;
+    T* base = (T*)(part == 0 ? p.q : (part == 1 ? p.k : p.v));
+    st4<T>(base + hh * p.qkv_hs + grow * kHeadDim + d, v);
+  } else if (EPI == EPI_RESID) {
+    float* x = p.x + grow * p.ldx + col;
+    const f32x4 old = *(const f32x4*)x;
+    float nv[4] = {old[0] + v[0], old[1] + v[1], old[2] + v[2], old[3] + v[3]};
+    st4<float>(x, nv);
+    if (p.out) {
+      if (p.out_f32) st4<float>((float*)p.out + grow * p.ldo + col, nv);
+      else st4<bf16>((bf16*)p.out + grow * p.ldo + col, nv);
+    }
+  } else {
+    float gv[4] = {gelu_erf(v[0]), gelu_erf(v[1]), gelu_erf(v[2]), gelu_erf(v[3])};
+    st4<T>((T*)p.hid + (int64_t)r * p.ldh + col, gv);
+  }
+}
+
+// ------------------------------------------------------------------ BF16 MFMA
+// 128 x 128 output tile, BK = 64, 4 waves in a 2 x 2 grid of 64 x 64 wave
+// tiles (2 x 2 MFMA 32x32x16 blocks each).  A and W tiles are staged in LDS
+// with 16-byte granules XOR-swizzled by row; the accumulators go through LDS
+// once more so that the epilogue reads and writes whole rows.
+template <int EPI>
+__global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
+  constexpr int BM = 128, BN = 128, BK = 64, CLD = BN + 4;
+  __shared__ __attribute__((aligned(16))) char smem[BM * CLD * 4];
+  bf16* As = (bf16*)smem;
+  bf16* Ws = As + 2 * BM * BK;
+  float* Cs = (float*)smem;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 5, r32 = lane & 31;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const bf16* A = (const bf16*)p.a;
+  const bf16* W = (const bf16*)p.w;
+  const bf16x8 zero8 = {};
+
+  bf16x8 areg[4], wreg[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = (tid >> 3) + 32 * i, ch = tid & 7;
+      areg[i] = (m0 + r < p.M) ? *(const bf16x8*)(A + (int64_t)(m0 + r) * p.lda + k0 + ch * 8) : zero8;
+      wreg[i] = *(const bf16x8*)(W + (int64_t)(n0 + r) * p.K + k0 + ch * 8);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = (tid >> 3) + 32 * i, ch = tid & 7;
+      *(bf16x8*)&As[buf * BM * BK + r * BK + ((ch ^ (r & 7)) * 8)] = areg[i];
+      *(bf16x8*)&Ws[buf * BN * BK + r * BK + ((ch ^ (r & 7)) * 8)] = wreg[i];
+    }
+  };
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
+
+  const int nk = p.K / BK;
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi) {
+        const int r = wm * 64 + mi * 32 + r32;
+        a[mi] = *(const bf16x8*)&As[buf * BM * BK + r * BK + (((2 * kk + g) ^ (r & 7)) * 8)];
+      }
+#pragma unroll
+      for (int nj = 0; nj < 2; ++nj) {
+        const int r = wn * 64 + nj * 32 + r32;
+        b[nj] = *(const bf16x8*)&Ws[buf * BN * BK + r * BK + (((2 * kk + g) ^ (r & 7)) * 8)];
+      }
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = mfma_bf16(a[mi], b[nj], acc[mi][nj]);
+    }
+    if (kt + 1 < nk) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int row = wm * 64 + mi * 32 + 8 * (i >> 2) + 4 * g + (i & 3);
+        const int col = wn * 64 + nj * 32 + r32;
+        Cs[row * CLD + col] = acc[mi][nj][i];
+      }
+  __syncthreads();
+  for (int idx = tid; idx < BM * (BN / 4); idx += 256) {
+    const int row = idx / (BN / 4), c4 = (idx % (BN / 4)) * 4;
+    if (m0 + row >= p.M) continue;
+    const f32x4 cv = *(const f32x4*)&Cs[row * CLD + c4];
+    float v[4] = {cv[0], cv[1], cv[2], cv[3]};
+    epi4<EPI, bf16>(p, m0 + row, n0 + c4, v);
+  }
+}
+
+// ------------------------------------------------------------------ FP32
+// Plain VALU tiled GEMM (64 x 64 tile, BK = 16, 4 x 4 outputs per thread); it
+// serves the float32 reference-precision path.
+template <int EPI>
+__global__ __launch_bounds__(256) void gemm_f32_kernel(GemmParams p) {
+  constexpr int BM = 64, BN = 64, BK = 16;
+  __shared__ float As[BK][BM + 4];
+  __shared__ float Ws[BK][BN + 4];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const float* A = (const float*)p.a;
+  const float* W = (const float*)p.w;
+  float acc[4][4] = {};
+  const int lr = tid >> 2, lk = (tid & 3) * 4;
+  for (int k0 = 0; k0 < p.K; k0 += BK) {
+    f32x4 av = {}, wv;
+    if (m0 + lr < p.M) av = *(const f32x4*)(A + (int64_t)(m0 + lr) * p.lda + k0 + lk);
+    wv = *(const f32x4*)(W + (int64_t)(n0 + lr) * p.K + k0 + lk);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      As[lk + j][lr] = av[j];
+      Ws[lk + j][lr] = wv[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BK; ++k) {
+      const f32x4 a = *(const f32x4*)&As[k][ty * 4];
+      const f32x4 b = *(const f32x4*)&Ws[k][tx * 4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_fmaf(a[i], b[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = m0 + ty * 4 + i;
+    if (row < p.M) epi4<EPI, float>(p, row, n0 + tx * 4, acc[i]);
+  }
+}
+
+hipError_t launch_gemm_bf16(const GemmParams& p, Epi epi, hipStream_t s) {
+  dim3 grid(p.N / 128, (p.M + 127) / 128), block(256);
+  switch (epi) {
+    case EPI_QKV: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_QKV>, grid, block, 0, s, p); break;
+    case EPI_RESID: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_RESID>, grid, block, 0, s, p); break;
+    case EPI_GELU: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_GELU>, grid, block, 0, s, p); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f32(const GemmParams& p, Epi epi, hipStream_t s) {
+  dim3 grid(p.N / 64, (p.M + 63) / 64), block(256);
+  switch (epi) {
+    case EPI_QKV: hipLaunchKernelGGL(gemm_f32_kernel<EPI_QKV>, grid, block, 0, s, p); break;
+    case EPI_RESID: hipLaunchKernelGGL(gemm_f32_kernel<EPI_RESID>, grid, block, 0, s, p); break;
+    case EPI_GELU: hipLaunchKernelGGL(gemm_f32_kernel<EPI_GELU>, grid, block, 0, s, p); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vggtx

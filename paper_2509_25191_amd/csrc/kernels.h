@@ -1,0 +1,87 @@
+// Host-visible launchers of the vggtx HIP kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace vggtx {
+
+// Sequence structure of one attention launch.  Either `uniform` (n_seq
+// sequences of `len` tokens back to back from token `base`) or an explicit
+// list (at most kMaxSeqInline entries) in processing order; the list is
+// ordered longest-first so that the biggest scenes start first.
+struct SeqTable {
+  int n_seq;
+  int uniform;
+  int len;             // uniform: tokens per sequence
+  int base;            // uniform: first token
+  int tiles_per_seq;   // uniform: query tiles per sequence
+  int start[kMaxSeqInline];     // list: first token
+  int end[kMaxSeqInline];       // list: one past the last token
+  int vt_base[kMaxSeqInline];   // list: padded column of the first token in transposed V
+  int blk_base[kMaxSeqInline];  // list: first FP8 scale block
+  int tile_end[kMaxSeqInline];  // list: inclusive prefix sum of query tiles
+};
+
+struct AttnParams {
+  const void* q; int64_t q_ts, q_hs;     // [tokens, H, D] strides in elements
+  const void* k; int64_t k_ts, k_hs;
+  const void* v; int64_t v_ts, v_hs;     // key-major V (float32 kernel)
+  const void* vt; int64_t vt_hs, vt_ds;  // transposed, padded V: (h, d, col) at h*vt_hs + d*vt_ds + col
+  void* o; int64_t o_ts, o_hs;
+  // FP8 scales: [H, n_blocks] (per-head stride sc_hs)
+  const float* sq; const float* sk; const float* sv; int64_t sc_hs;
+  const float* vmax;                     // FP8: per-head max of the V scales
+  float scale_log2;                      // log2(e) / sqrt(D)
+  int n_items;                           // query tiles per head
+  SeqTable seqs;
+};
+
+// ---- attention (attention.hip)
+hipError_t launch_attn_bf16(const AttnParams& p, int H, int qb_per_wave, bool out_f32, hipStream_t s);
+hipError_t launch_attn_f32(const AttnParams& p, int H, hipStream_t s);
+hipError_t launch_attn_fp8(const AttnParams& p, int H, hipStream_t s);
+int attn_block_rows(int prec, int qb_per_wave);  // query rows per work item
+
+// Transposed, zero-padded copy of V: v [tokens, H, D] (bf16 or u8 codes) ->
+// vt [H, D, padded tokens].
+hipError_t launch_v_transpose_bf16(const bf16* v, int64_t v_ts, int64_t v_hs, bf16* vt, int64_t vt_hs,
+                                   int64_t vt_ds, const SeqTable& seqs, int n_tiles, int H, hipStream_t s);
+
+// FP8 quantiser: x [tokens, H, D] bf16 -> codes and per-(head, 128-row block) scales.
+// transposed == false: codes [H, tokens, D] (row-major, c_hs = tokens*D)
+// transposed == true:  codes [H, D, padded tokens] like vt above (zero padding).
+hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, uint8_t* codes, int64_t c_hs,
+                            int64_t c_ds, bool transposed, float* scales, int64_t sc_hs,
+                            const SeqTable& seqs, int n_blocks, int H, hipStream_t s);
+// per-head max over n_blocks scales -> vmax[H]
+hipError_t launch_scale_max(const float* scales, int64_t sc_hs, int n_blocks, float* vmax, int H, hipStream_t s);
+
+// ---- GEMMs (gemm.hip): C[M, N] = A[M, K] W[N, K]^T + bias, then an epilogue
+enum Epi { EPI_QKV = 0, EPI_RESID = 1, EPI_GELU = 2 };
+
+struct GemmParams {
+  const void* a; int64_t lda;      // A rows (bf16 or f32)
+  const void* w;                   // W [N, K] row-major (bf16 or f32)
+  const void* bias;                // [N] (bf16 or f32)
+  int M, N, K;
+  int row0;                        // global token index of A's first row
+  // EPI_QKV: q, k, v [H, n_tokens, D] (bf16 or f32); C = H*D
+  void* q; void* k; void* v; int64_t qkv_hs; int C;
+  // EPI_RESID: x[row0 + r, c] += result (float32, leading dim ldx); optional copy to out
+  float* x; int64_t ldx;
+  void* out; int64_t ldo; int out_f32;
+  // EPI_GELU: hid[r, c] = gelu(result)
+  void* hid; int64_t ldh;
+};
+
+hipError_t launch_gemm_bf16(const GemmParams& p, Epi epi, hipStream_t s);
+hipError_t launch_gemm_f32(const GemmParams& p, Epi epi, hipStream_t s);
+
+// ---- LayerNorm (elementwise.hip): h[r] = LN(x[row0 + r]) for r < rows
+hipError_t launch_layernorm(const float* x, int64_t ldx, const void* g, const void* b, float eps, void* h,
+                            int64_t ldh, int rows, int C, bool bf16_io, hipStream_t s);
+hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
+
+}  // namespace vggtx

@@ -1,0 +1,840 @@
+// C-ABI of the vggtx library: argument validation, workspace carving, the
+// layer loop with output-layer selection and frame chunking, and the
+// attention entry points.  See include/vggtx.h for the contract.
+//
+// Method anchors (arXiv 2509.25191, Sec. 3.2): alternating frame / global
+// attention layers; only the requested layers' outputs are kept (everything
+// else is overwritten in place in the workspace); token-local work and frame
+// attention run over chunks of `frame_chunk` frames (chunk 128 in Sec. 4.1),
+// which bounds the scratch for the MLP hidden activations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vggtx.h"
+#include "kernels.h"
+
+using namespace vggtx;
+
+// Kernel timing record of a handle (see vggtx_timing_enable).
+struct KernelTimer {
+  static constexpr int kMaxRec = 4096;
+  bool enabled = false;
+  std::vector<hipEvent_t> ev;  // start/end pairs
+  std::vector<int> cls;
+  std::vector<double> flops;
+  int64_t dropped = 0;
+};
+
+struct vggtx_ctx {
+  int device;
+  vggtx_config cfg;
+  KernelTimer timer;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+vggtx_status fail(vggtx_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define VGGTX_HIP(call)                                                                        \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess) return fail(VGGTX_E_HIP, "%s: %s", #call, hipGetErrorString(e_));   \
+  } while (0)
+
+#define VGGTX_TRY(expr)                    \
+  do {                                     \
+    vggtx_status s_ = (expr);              \
+    if (s_ != VGGTX_OK) return s_;         \
+  } while (0)
+
+// Switch to the handle's device for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+// Brackets the launches issued during its lifetime with timing events when
+// the handle's timer is enabled.
+struct Span {
+  vggtx_ctx* c;
+  int idx = -1;
+  hipStream_t s;
+  Span(vggtx_ctx* ctx, int cls, double flops, hipStream_t st) : c(ctx), s(st) {
+    KernelTimer& t = c->timer;
+    if (!t.enabled) return;
+    const int n = (int)t.cls.size();
+    if (n >= KernelTimer::kMaxRec) {
+      ++t.dropped;
+      return;
+    }
+    if (hipEventRecord(t.ev[2 * n], s) != hipSuccess) return;
+    idx = n;
+    t.cls.push_back(cls);
+    t.flops.push_back(flops);
+  }
+  ~Span() {
+    if (idx >= 0) (void)hipEventRecord(c->timer.ev[2 * idx + 1], s);
+  }
+};
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+inline int64_t cdiv(int64_t x, int64_t m) { return (x + m - 1) / m; }
+
+// -------------------------------------------------------------- sequences
+// A set of back-to-back sequences (frames or scenes) in storage order.
+struct Seqs {
+  bool uniform = false;
+  int first = 0;     // first token
+  int len = 0;       // uniform length
+  int n = 0;         // number of sequences
+  int first_index = 0;  // uniform: index of the first sequence (for padded-column and block numbering)
+  std::vector<int> start, end;  // list form
+
+  int64_t tokens() const { return uniform ? (int64_t)n * len : (n ? end.back() - start.front() : 0); }
+  int64_t padded_cols() const {
+    if (uniform) return (int64_t)n * round_up(len, kKeyPad);
+    int64_t c = 0;
+    for (int i = 0; i < n; ++i) c += round_up(end[i] - start[i], kKeyPad);
+    return c;
+  }
+  int64_t scale_blocks() const {
+    if (uniform) return (int64_t)n * cdiv(len, kQuantRows);
+    int64_t c = 0;
+    for (int i = 0; i < n; ++i) c += cdiv(end[i] - start[i], kQuantRows);
+    return c;
+  }
+};
+
+// Build the launch tables for tiles of `rows` tokens.  List-form sequence sets
+// are split into groups of at most kMaxSeqInline sequences, each group ordered
+// longest-first.
+std::vector<std::pair<SeqTable, int>> make_tables(const Seqs& s, int rows) {
+  std::vector<std::pair<SeqTable, int>> out;
+  if (s.n == 0) return out;
+  if (s.uniform) {
+    SeqTable t;
+    memset(&t, 0, sizeof(t));
+    t.uniform = 1;
+    t.n_seq = s.n;
+    t.len = s.len;
+    t.tiles_per_seq = (int)cdiv(s.len, rows);
+    t.start[0] = s.first;
+    t.vt_base[0] = (int)((int64_t)s.first_index * round_up(s.len, kKeyPad));
+    t.blk_base[0] = (int)((int64_t)s.first_index * cdiv(s.len, kQuantRows));
+    out.push_back({t, t.n_seq * t.tiles_per_seq});
+    return out;
+  }
+  std::vector<int> vb(s.n), bb(s.n);
+  int64_t c = 0, b = 0;
+  for (int i = 0; i < s.n; ++i) {
+    vb[i] = (int)c;
+    bb[i] = (int)b;
+    c += round_up(s.end[i] - s.start[i], kKeyPad);
+    b += cdiv(s.end[i] - s.start[i], kQuantRows);
+  }
+  for (int g0 = 0; g0 < s.n; g0 += kMaxSeqInline) {
+    const int g1 = std::min(s.n, g0 + kMaxSeqInline);
+    std::vector<int> idx;
+    for (int i = g0; i < g1; ++i)
+      if (s.end[i] > s.start[i]) idx.push_back(i);
+    if (idx.empty()) continue;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b2) {
+      return (s.end[a] - s.start[a]) > (s.end[b2] - s.start[b2]);
+    });
+    SeqTable t;
+    memset(&t, 0, sizeof(t));
+    t.uniform = 0;
+    t.n_seq = (int)idx.size();
+    int acc = 0;
+    for (int j = 0; j < t.n_seq; ++j) {
+      const int i = idx[j];
+      t.start[j] = s.start[i];
+      t.end[j] = s.end[i];
+      t.vt_base[j] = vb[i];
+      t.blk_base[j] = bb[i];
+      acc += (int)cdiv(s.end[i] - s.start[i], rows);
+      t.tile_end[j] = acc;
+    }
+    out.push_back({t, acc});
+  }
+  return out;
+}
+
+// -------------------------------------------------------------- workspace
+struct Ws {
+  float* x = nullptr;        // residual stream [N, C] f32
+  void* q = nullptr;         // [H, N, D] bf16 (f32 for the F32 path)
+  void* k = nullptr;
+  void* v = nullptr;
+  bf16* vt = nullptr;        // [H, D, Npad] bf16
+  void* o = nullptr;         // [N, C] bf16 / f32
+  void* h = nullptr;         // [R, C] bf16 / f32
+  void* hid = nullptr;       // [R, F] bf16 / f32
+  uint8_t* q8 = nullptr;     // FP8 codes [H, N, D]
+  uint8_t* k8 = nullptr;
+  uint8_t* v8t = nullptr;    // [H, D, Npad]
+  float* sq = nullptr;       // [H, nblk]
+  float* sk = nullptr;
+  float* sv = nullptr;
+  float* vmax = nullptr;     // [H]
+  size_t total = 0;
+};
+
+struct WsShape {
+  int64_t n_tokens, npad, nblk, chunk_rows;
+};
+
+Ws carve(const vggtx_config& c, const WsShape& sh, vggtx_prec prec, char* base, bool with_x = true) {
+  Ws w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off += (size_t)round_up((int64_t)bytes, 256);
+    return p;
+  };
+  const int64_t N = sh.n_tokens, C = c.dim, F = c.mlp_hidden, R = sh.chunk_rows;
+  const size_t el = prec == VGGTX_F32 ? 4 : 2;
+  if (with_x) w.x = (float*)take(N * C * 4);
+  w.q = take(N * C * el);
+  w.k = take(N * C * el);
+  w.v = take(N * C * el);
+  if (prec != VGGTX_F32) w.vt = (bf16*)take(C * sh.npad * 2);
+  w.o = take(N * C * el);
+  w.h = take(R * C * el);
+  w.hid = take(R * F * el);
+  if (prec == VGGTX_FP8_E4M3) {
+    w.q8 = (uint8_t*)take(N * C);
+    w.k8 = (uint8_t*)take(N * C);
+    w.v8t = (uint8_t*)take(C * sh.npad);
+    const int64_t H = c.heads;
+    w.sq = (float*)take(H * sh.nblk * 4);
+    w.sk = (float*)take(H * sh.nblk * 4);
+    w.sv = (float*)take(H * sh.nblk * 4);
+    w.vmax = (float*)take(H * 4);
+  }
+  w.total = off;
+  return w;
+}
+
+// -------------------------------------------------------------- validation
+vggtx_status check_cfg(const vggtx_config* c) {
+  if (!c) return fail(VGGTX_E_INVALID, "config is null");
+  if (c->head_dim != kHeadDim) return fail(VGGTX_E_UNSUPPORTED, "head_dim %d: only 64 is supported", c->head_dim);
+  if (c->heads <= 0 || c->dim != c->heads * c->head_dim)
+    return fail(VGGTX_E_INVALID, "dim %d != heads %d * head_dim %d", c->dim, c->heads, c->head_dim);
+  if (c->dim % 128 || c->dim > 2048) return fail(VGGTX_E_UNSUPPORTED, "dim %d: must be a multiple of 128, <= 2048", c->dim);
+  if (c->mlp_hidden <= 0 || c->mlp_hidden % 128)
+    return fail(VGGTX_E_UNSUPPORTED, "mlp_hidden %d: must be a positive multiple of 128", c->mlp_hidden);
+  if (!(c->ln_eps > 0.f)) return fail(VGGTX_E_INVALID, "ln_eps must be positive");
+  if (c->frame_chunk <= 0) return fail(VGGTX_E_INVALID, "frame_chunk must be positive");
+  return VGGTX_OK;
+}
+
+vggtx_status check_prec(vggtx_prec p) {
+  if (p != VGGTX_F32 && p != VGGTX_BF16 && p != VGGTX_FP8_E4M3) return fail(VGGTX_E_INVALID, "unknown precision %d", (int)p);
+  return VGGTX_OK;
+}
+
+vggtx_status check_block_w(const vggtx_block_w& w, const char* what, int layer) {
+  const void* ptrs[12] = {w.ln1_g, w.ln1_b, w.w_qkv, w.b_qkv, w.w_o, w.b_o, w.ln2_g, w.ln2_b, w.w_fc1, w.b_fc1, w.w_fc2, w.b_fc2};
+  for (int i = 0; i < 12; ++i) {
+    if (!ptrs[i]) return fail(VGGTX_E_INVALID, "layer %d %s block: parameter %d is null", layer, what, i);
+    if (((uintptr_t)ptrs[i]) % 16) return fail(VGGTX_E_INVALID, "layer %d %s block: parameter %d not 16-byte aligned", layer, what, i);
+  }
+  return VGGTX_OK;
+}
+
+// Largest number of tokens whose indices the kernels address with 32-bit ints.
+constexpr int64_t kMaxTokens = (int64_t)1 << 30;
+
+// -------------------------------------------------------------- block forward
+struct BlockRun {
+  vggtx_ctx* ctx;
+  vggtx_prec prec;
+  Ws ws;
+  int64_t N;           // tokens in the x buffer
+  hipStream_t stream;
+};
+
+inline bool lowp(vggtx_prec p) { return p != VGGTX_F32; }
+
+// out phase over rows [r0, r1): x += O W_o^T + b_o; x += MLP(LN2(x)); optional output copy
+vggtx_status out_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, int64_t r1, void* out, int64_t ldo,
+                       bool out_f32) {
+  const vggtx_config& c = br.ctx->cfg;
+  const int C = c.dim, F = c.mlp_hidden;
+  const bool lp = lowp(br.prec);
+  const size_t el = lp ? 2 : 4;
+  auto gemm = lp ? launch_gemm_bf16 : launch_gemm_f32;
+  const int M = (int)(r1 - r0);
+  GemmParams g;
+  memset(&g, 0, sizeof(g));
+  g.a = (const char*)br.ws.o + r0 * C * el;
+  g.lda = C;
+  g.w = w.w_o;
+  g.bias = w.b_o;
+  g.M = M; g.N = C; g.K = C;
+  g.row0 = (int)r0;
+  g.x = br.ws.x; g.ldx = C;
+  {
+    Span sp(br.ctx, VGGTX_K_GEMM, 2.0 * M * C * C, br.stream);
+    VGGTX_HIP(gemm(g, EPI_RESID, br.stream));
+  }
+  {
+    Span sp(br.ctx, VGGTX_K_OTHER, 0.0, br.stream);
+    VGGTX_HIP(launch_layernorm(br.ws.x + r0 * C, C, w.ln2_g, w.ln2_b, c.ln_eps, br.ws.h, C, M, C, lp, br.stream));
+  }
+  memset(&g, 0, sizeof(g));
+  g.a = br.ws.h; g.lda = C;
+  g.w = w.w_fc1; g.bias = w.b_fc1;
+  g.M = M; g.N = F; g.K = C;
+  g.row0 = (int)r0;
+  g.hid = br.ws.hid; g.ldh = F;
+  {
+    Span sp(br.ctx, VGGTX_K_GEMM, 2.0 * M * F * C, br.stream);
+    VGGTX_HIP(gemm(g, EPI_GELU, br.stream));
+  }
+  memset(&g, 0, sizeof(g));
+  g.a = br.ws.hid; g.lda = F;
+  g.w = w.w_fc2; g.bias = w.b_fc2;
+  g.M = M; g.N = C; g.K = F;
+  g.row0 = (int)r0;
+  g.x = br.ws.x; g.ldx = C;
+  g.out = out; g.ldo = ldo; g.out_f32 = out_f32 ? 1 : 0;
+  {
+    Span sp(br.ctx, VGGTX_K_GEMM, 2.0 * M * C * F, br.stream);
+    VGGTX_HIP(gemm(g, EPI_RESID, br.stream));
+  }
+  return VGGTX_OK;
+}
+
+// LN1 + QKV projection of rows [r0, r1) into the head-major q/k/v buffers.
+vggtx_status qkv_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, int64_t r1) {
+  const vggtx_config& c = br.ctx->cfg;
+  const int C = c.dim;
+  const bool lp = lowp(br.prec);
+  const int M = (int)(r1 - r0);
+  {
+    Span sp(br.ctx, VGGTX_K_OTHER, 0.0, br.stream);
+    VGGTX_HIP(launch_layernorm(br.ws.x + r0 * C, C, w.ln1_g, w.ln1_b, c.ln_eps, br.ws.h, C, M, C, lp, br.stream));
+  }
+  GemmParams g;
+  memset(&g, 0, sizeof(g));
+  g.a = br.ws.h; g.lda = C;
+  g.w = w.w_qkv; g.bias = w.b_qkv;
+  g.M = M; g.N = 3 * C; g.K = C;
+  g.row0 = (int)r0;
+  g.q = br.ws.q; g.k = br.ws.k; g.v = br.ws.v;
+  g.qkv_hs = br.N * kHeadDim;
+  g.C = C;
+  Span sp(br.ctx, VGGTX_K_GEMM, 2.0 * M * 3 * C * C, br.stream);
+  VGGTX_HIP((lp ? launch_gemm_bf16 : launch_gemm_f32)(g, EPI_QKV, br.stream));
+  return VGGTX_OK;
+}
+
+
+// Operands of one attention pass: q/k/v/o with their strides plus the
+// workspace pieces the BF16 (vt) and FP8 (codes, scales) kernels need.
+struct AttnIO {
+  const void* q; int64_t q_ts, q_hs;
+  const void* k; int64_t k_ts, k_hs;
+  const void* v; int64_t v_ts, v_hs;
+  void* o; int64_t o_ts, o_hs;
+  bf16* vt;
+  uint8_t *q8, *k8, *v8t;
+  float *sq, *sk, *sv, *vmax;
+  int64_t npad;     // columns of vt / v8t
+  int64_t nblk;     // per-head stride of the FP8 scale arrays
+  int64_t n_tokens; // rows of the q8 / k8 code arrays
+};
+
+double table_flops(const SeqTable& t, int H) {
+  double sq = 0.0;
+  if (t.uniform) sq = (double)t.n_seq * (double)t.len * (double)t.len;
+  else
+    for (int i = 0; i < t.n_seq; ++i) sq += (double)(t.end[i] - t.start[i]) * (double)(t.end[i] - t.start[i]);
+  return 4.0 * kHeadDim * H * sq;
+}
+
+// Attention over the sequence set `s`: o = softmax(q k^T / sqrt(D)) v per
+// sequence and head.  `prec` picks the kernel; FP8 quantises q, k, v into
+// the workspace first (per-sequence 128-row blocks), BF16 transposes v.
+vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs& s, int H, vggtx_prec prec,
+                           hipStream_t st) {
+  AttnParams p;
+  memset(&p, 0, sizeof(p));
+  p.q = io.q; p.q_ts = io.q_ts; p.q_hs = io.q_hs;
+  p.k = io.k; p.k_ts = io.k_ts; p.k_hs = io.k_hs;
+  p.v = io.v; p.v_ts = io.v_ts; p.v_hs = io.v_hs;
+  p.o = io.o; p.o_ts = io.o_ts; p.o_hs = io.o_hs;
+  p.scale_log2 = kLog2e / sqrtf((float)kHeadDim);
+  if (prec == VGGTX_F32) {
+    for (auto& tn : make_tables(s, attn_block_rows(0, 1))) {
+      p.seqs = tn.first; p.n_items = tn.second;
+      Span sp(ctx, cls, table_flops(tn.first, H), st);
+      VGGTX_HIP(launch_attn_f32(p, H, st));
+    }
+    return VGGTX_OK;
+  }
+  p.vt_hs = (int64_t)kHeadDim * io.npad; p.vt_ds = io.npad;
+  if (prec == VGGTX_BF16) {
+    {
+      Span sp(ctx, VGGTX_K_OTHER, 0.0, st);
+      for (auto& tn : make_tables(s, 64))
+        VGGTX_HIP(launch_v_transpose_bf16((const bf16*)io.v, io.v_ts, io.v_hs, io.vt, p.vt_hs, p.vt_ds, tn.first,
+                                          tn.second, H, st));
+    }
+    p.vt = io.vt;
+    for (auto& tn : make_tables(s, attn_block_rows(1, 1))) {
+      p.seqs = tn.first; p.n_items = tn.second;
+      Span sp(ctx, cls, table_flops(tn.first, H), st);
+      VGGTX_HIP(launch_attn_bf16(p, H, 1, false, st));
+    }
+    return VGGTX_OK;
+  }
+  const int64_t N = io.n_tokens;
+  {
+    Span sp(ctx, VGGTX_K_OTHER, 0.0, st);
+    for (auto& tn : make_tables(s, kQuantRows)) {
+      VGGTX_HIP(launch_quant_fp8((const bf16*)io.q, io.q_ts, io.q_hs, io.q8, N * kHeadDim, 0, false, io.sq, io.nblk,
+                                 tn.first, tn.second, H, st));
+      VGGTX_HIP(launch_quant_fp8((const bf16*)io.k, io.k_ts, io.k_hs, io.k8, N * kHeadDim, 0, false, io.sk, io.nblk,
+                                 tn.first, tn.second, H, st));
+      VGGTX_HIP(launch_quant_fp8((const bf16*)io.v, io.v_ts, io.v_hs, io.v8t, (int64_t)kHeadDim * io.npad, io.npad,
+                                 true, io.sv, io.nblk, tn.first, tn.second, H, st));
+    }
+    VGGTX_HIP(launch_scale_max(io.sv, io.nblk, (int)s.scale_blocks(), io.vmax, H, st));
+  }
+  p.q = io.q8; p.q_ts = kHeadDim; p.q_hs = N * kHeadDim;
+  p.k = io.k8; p.k_ts = kHeadDim; p.k_hs = N * kHeadDim;
+  p.vt = io.v8t;
+  p.sq = io.sq; p.sk = io.sk; p.sv = io.sv; p.sc_hs = io.nblk; p.vmax = io.vmax;
+  for (auto& tn : make_tables(s, attn_block_rows(2, 1))) {
+    p.seqs = tn.first; p.n_items = tn.second;
+    Span sp(ctx, cls, table_flops(tn.first, H), st);
+    VGGTX_HIP(launch_attn_fp8(p, H, st));
+  }
+  return VGGTX_OK;
+}
+
+// Attention of a block over the sequence set `s` from the head-major q/k/v
+// workspace buffers into o [N, C].
+vggtx_status attn_phase(const BlockRun& br, const Seqs& s, bool fp8, int64_t npad, int64_t nblk, int cls) {
+  const vggtx_config& c = br.ctx->cfg;
+  const int64_t N = br.N;
+  AttnIO io;
+  memset(&io, 0, sizeof(io));
+  io.q = br.ws.q; io.q_ts = kHeadDim; io.q_hs = N * kHeadDim;
+  io.k = br.ws.k; io.k_ts = kHeadDim; io.k_hs = N * kHeadDim;
+  io.v = br.ws.v; io.v_ts = kHeadDim; io.v_hs = N * kHeadDim;
+  io.o = br.ws.o; io.o_ts = c.dim; io.o_hs = kHeadDim;
+  io.vt = br.ws.vt;
+  io.q8 = br.ws.q8; io.k8 = br.ws.k8; io.v8t = br.ws.v8t;
+  io.sq = br.ws.sq; io.sk = br.ws.sk; io.sv = br.ws.sv; io.vmax = br.ws.vmax;
+  io.npad = npad; io.nblk = nblk; io.n_tokens = N;
+  const vggtx_prec prec = br.prec == VGGTX_F32 ? VGGTX_F32 : (fp8 ? VGGTX_FP8_E4M3 : VGGTX_BF16);
+  return run_attention(br.ctx, cls, io, s, c.heads, prec, br.stream);
+}
+
+// One block whose attention spans the sequence set `seqs` (rows [0, N) of x):
+// QKV for every chunk, one attention pass, then the output phase per chunk.
+vggtx_status block_global(const BlockRun& br, const vggtx_block_w& w, const Seqs& seqs, int64_t chunk_rows, bool fp8,
+                          int64_t npad, int64_t nblk, void* out, int64_t ldo, bool out_f32) {
+  for (int64_t r0 = 0; r0 < br.N; r0 += chunk_rows) VGGTX_TRY(qkv_phase(br, w, r0, std::min(br.N, r0 + chunk_rows)));
+  VGGTX_TRY(attn_phase(br, seqs, fp8, npad, nblk, VGGTX_K_ATTN_GLOBAL));
+  for (int64_t r0 = 0; r0 < br.N; r0 += chunk_rows)
+    VGGTX_TRY(out_phase(br, w, r0, std::min(br.N, r0 + chunk_rows), out, ldo, out_f32));
+  return VGGTX_OK;
+}
+
+// Frame block: chunks of whole frames; every chunk runs QKV, frame attention
+// and the output phase before the next chunk starts (Sec. 3.2, chunked
+// frame-wise processing).
+vggtx_status block_frames(const BlockRun& br, const vggtx_block_w& w, int S, int P, int frame_chunk, int64_t npad,
+                          int64_t nblk, void* out, int64_t ldo, bool out_f32) {
+  for (int f0 = 0; f0 < S; f0 += frame_chunk) {
+    const int f1 = std::min(S, f0 + frame_chunk);
+    const int64_t r0 = (int64_t)f0 * P, r1 = (int64_t)f1 * P;
+    VGGTX_TRY(qkv_phase(br, w, r0, r1));
+    Seqs fr;
+    fr.uniform = true; fr.first = (int)r0; fr.len = P; fr.n = f1 - f0; fr.first_index = f0;
+    VGGTX_TRY(attn_phase(br, fr, false, npad, nblk, VGGTX_K_ATTN_FRAME));
+    VGGTX_TRY(out_phase(br, w, r0, r1, out, ldo, out_f32));
+  }
+  return VGGTX_OK;
+}
+
+vggtx_status check_offsets(const int32_t* off, int n, const char* what) {
+  if (!off) return fail(VGGTX_E_INVALID, "%s offsets are null", what);
+  if (n < 1) return fail(VGGTX_E_INVALID, "%s count %d < 1", what, n);
+  if (off[0] != 0) return fail(VGGTX_E_INVALID, "%s offsets must start at 0", what);
+  for (int i = 0; i < n; ++i)
+    if (off[i + 1] < off[i]) return fail(VGGTX_E_INVALID, "%s offsets decrease at %d", what, i);
+  return VGGTX_OK;
+}
+
+Seqs seqs_from_offsets(const int32_t* off, int n, int scale) {
+  Seqs s;
+  if (n == 1) {
+    s.uniform = true; s.first = 0; s.len = off[1] * scale; s.n = s.len > 0 ? 1 : 0; s.first_index = 0;
+    return s;
+  }
+  s.uniform = false; s.n = n;
+  for (int i = 0; i < n; ++i) {
+    s.start.push_back(off[i] * scale);
+    s.end.push_back(off[i + 1] * scale);
+  }
+  return s;
+}
+
+WsShape agg_shape(const vggtx_config& c, int64_t total_frames, int P) {
+  WsShape sh;
+  sh.n_tokens = total_frames * P;
+  // padded columns of frame-wise sets bound those of any scene partition
+  sh.npad = total_frames * round_up(P, kKeyPad);
+  sh.nblk = total_frames * cdiv(P, kQuantRows);
+  sh.chunk_rows = std::min<int64_t>(total_frames, c.frame_chunk) * P;
+  return sh;
+}
+
+vggtx_status aggregate_impl(vggtx_handle h, const float* tokens, const int32_t* frame_offsets, int n_scenes, int P,
+                            const vggtx_pair_w* w, int depth, const int32_t* out_layers, int n_out, void* out,
+                            vggtx_dtype out_dtype, vggtx_prec prec, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  VGGTX_TRY(check_prec(prec));
+  VGGTX_TRY(check_offsets(frame_offsets, n_scenes, "frame"));
+  const vggtx_config& c = h->cfg;
+  if (P <= 0) return fail(VGGTX_E_INVALID, "P = %d must be positive", P);
+  const int64_t S = frame_offsets[n_scenes];
+  const int64_t N = S * P;
+  if (N > kMaxTokens) return fail(VGGTX_E_UNSUPPORTED, "%lld tokens exceed the supported %lld", (long long)N, (long long)kMaxTokens);
+  if (depth <= 0 || !w) return fail(VGGTX_E_INVALID, "depth %d / weights %p", depth, (const void*)w);
+  if (n_out <= 0 || !out_layers) return fail(VGGTX_E_INVALID, "n_out %d / out_layers %p", n_out, (const void*)out_layers);
+  for (int i = 0; i < n_out; ++i) {
+    if (out_layers[i] < 0 || out_layers[i] >= depth)
+      return fail(VGGTX_E_INVALID, "out_layers[%d] = %d outside [0, %d)", i, out_layers[i], depth);
+    if (i && out_layers[i] <= out_layers[i - 1]) return fail(VGGTX_E_INVALID, "out_layers must be strictly increasing");
+  }
+  if (out_dtype != VGGTX_OUT_F32 && out_dtype != VGGTX_OUT_BF16) return fail(VGGTX_E_INVALID, "unknown out dtype");
+  if (N == 0) return VGGTX_OK;
+  if (!tokens || !out) return fail(VGGTX_E_INVALID, "tokens %p / out %p is null", (const void*)tokens, out);
+  if ((uintptr_t)tokens % 16 || (uintptr_t)out % 16) return fail(VGGTX_E_INVALID, "tokens / out must be 16-byte aligned");
+  const int last = out_layers[n_out - 1];
+  for (int l = 0; l <= last; ++l) {
+    VGGTX_TRY(check_block_w(w[l].frame, "frame", l));
+    VGGTX_TRY(check_block_w(w[l].global, "global", l));
+  }
+  const WsShape sh = agg_shape(c, S, P);
+  const Ws need = carve(c, sh, prec, nullptr);
+  if (!ws || ws_bytes < need.total)
+    return fail(VGGTX_E_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need.total);
+  if ((uintptr_t)ws % 256) return fail(VGGTX_E_INVALID, "workspace must be 256-byte aligned");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+
+  BlockRun br;
+  br.ctx = h;
+  br.prec = prec;
+  br.ws = carve(c, sh, prec, (char*)ws);
+  br.N = N;
+  br.stream = (hipStream_t)stream;
+  const int C = c.dim;
+  VGGTX_HIP(launch_copy_f32(tokens, br.ws.x, N * C, br.stream));
+  const Seqs scenes = seqs_from_offsets(frame_offsets, n_scenes, P);
+  const bool out_f32 = out_dtype == VGGTX_OUT_F32;
+  const size_t oel = out_f32 ? 4 : 2;
+  int slot = 0;
+  for (int l = 0; l <= last; ++l) {
+    const bool keep = out_layers[slot] == l;
+    char* ob = keep ? (char*)out + (size_t)slot * N * 2 * C * oel : nullptr;
+    VGGTX_TRY(block_frames(br, w[l].frame, (int)S, P, c.frame_chunk, sh.npad, sh.nblk, ob, 2 * C, out_f32));
+    VGGTX_TRY(block_global(br, w[l].global, scenes, sh.chunk_rows, prec == VGGTX_FP8_E4M3, sh.npad, sh.nblk,
+                           ob ? ob + (size_t)C * oel : nullptr, 2 * C, out_f32));
+    if (keep) ++slot;
+  }
+  return VGGTX_OK;
+}
+
+vggtx_status check_layout(const vggtx_layout& l, int H, const char* what) {
+  if (l.token_stride <= 0 || l.head_stride <= 0 || l.token_stride % 8 || l.head_stride % 8)
+    return fail(VGGTX_E_INVALID, "%s layout strides (%lld, %lld) must be positive multiples of 8", what,
+                (long long)l.token_stride, (long long)l.head_stride);
+  (void)H;
+  return VGGTX_OK;
+}
+
+Ws carve_attn(int H, int64_t N, int64_t npad, int64_t nblk, vggtx_prec prec, char* base) {
+  Ws w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off += (size_t)round_up((int64_t)bytes, 256);
+    return p;
+  };
+  const int64_t C = (int64_t)H * kHeadDim;
+  if (prec == VGGTX_BF16) w.vt = (bf16*)take(C * npad * 2);
+  if (prec == VGGTX_FP8_E4M3) {
+    w.q8 = (uint8_t*)take(N * C);
+    w.k8 = (uint8_t*)take(N * C);
+    w.v8t = (uint8_t*)take(C * npad);
+    w.sq = (float*)take(H * nblk * 4);
+    w.sk = (float*)take(H * nblk * 4);
+    w.sv = (float*)take(H * nblk * 4);
+    w.vmax = (float*)take(H * 4);
+  }
+  w.total = off;
+  return w;
+}
+
+vggtx_status attn_entry(vggtx_handle h, int cls, const void* q, const void* k, const void* v, void* o, const Seqs& s,
+                        int H, int D, vggtx_layout in, vggtx_layout ol, vggtx_prec prec, void* ws, size_t ws_bytes,
+                        void* stream) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  VGGTX_TRY(check_prec(prec));
+  if (D != kHeadDim) return fail(VGGTX_E_UNSUPPORTED, "head dim %d: only 64 is supported", D);
+  if (H <= 0) return fail(VGGTX_E_INVALID, "H = %d", H);
+  VGGTX_TRY(check_layout(in, H, "input"));
+  VGGTX_TRY(check_layout(ol, H, "output"));
+  const int64_t N = s.uniform ? (int64_t)s.first + s.tokens() : (s.n ? s.end.back() : 0);
+  if (N > kMaxTokens) return fail(VGGTX_E_UNSUPPORTED, "too many tokens");
+  if (N == 0) return VGGTX_OK;
+  if (!q || !k || !v || !o) return fail(VGGTX_E_INVALID, "q/k/v/o must not be null");
+  if ((uintptr_t)q % 16 || (uintptr_t)k % 16 || (uintptr_t)v % 16 || (uintptr_t)o % 16)
+    return fail(VGGTX_E_INVALID, "q/k/v/o must be 16-byte aligned");
+  const int64_t npad = s.padded_cols(), nblk = s.scale_blocks();
+  const Ws need = carve_attn(H, N, npad, nblk, prec, nullptr);
+  if (need.total && (!ws || ws_bytes < need.total))
+    return fail(VGGTX_E_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need.total);
+  if (ws && (uintptr_t)ws % 256) return fail(VGGTX_E_INVALID, "workspace must be 256-byte aligned");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+  const Ws w = carve_attn(H, N, npad, nblk, prec, (char*)ws);
+  AttnIO io;
+  memset(&io, 0, sizeof(io));
+  io.q = q; io.q_ts = in.token_stride; io.q_hs = in.head_stride;
+  io.k = k; io.k_ts = in.token_stride; io.k_hs = in.head_stride;
+  io.v = v; io.v_ts = in.token_stride; io.v_hs = in.head_stride;
+  io.o = o; io.o_ts = ol.token_stride; io.o_hs = ol.head_stride;
+  io.vt = w.vt;
+  io.q8 = w.q8; io.k8 = w.k8; io.v8t = w.v8t;
+  io.sq = w.sq; io.sk = w.sk; io.sv = w.sv; io.vmax = w.vmax;
+  io.npad = npad; io.nblk = nblk; io.n_tokens = N;
+  return run_attention(h, cls, io, s, H, prec, (hipStream_t)stream);
+}
+
+}  // namespace
+
+// ====================================================================== C-ABI
+extern "C" {
+
+vggtx_status vggtx_create(vggtx_handle* h, int device, const vggtx_config* cfg) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle output pointer is null");
+  *h = nullptr;
+  VGGTX_TRY(check_cfg(cfg));
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(VGGTX_E_NODEVICE, "no HIP device");
+  if (device < 0 || device >= n) return fail(VGGTX_E_NODEVICE, "device %d of %d", device, n);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(VGGTX_E_NODEVICE, "cannot query device %d", device);
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(VGGTX_E_UNSUPPORTED, "device %d is %s; the kernels are built for gfx950", device, prop.gcnArchName);
+  vggtx_ctx* c = new (std::nothrow) vggtx_ctx;
+  if (!c) return fail(VGGTX_E_INVALID, "out of host memory");
+  c->device = device;
+  c->cfg = *cfg;
+  *h = c;
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_destroy(vggtx_handle h) {
+  if (!h) return VGGTX_OK;
+  for (auto& e : h->timer.ev) (void)hipEventDestroy(e);
+  delete h;
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_workspace_size(vggtx_handle h, int total_frames, int P, vggtx_prec prec, size_t* bytes) {
+  if (!h || !bytes) return fail(VGGTX_E_INVALID, "handle / bytes is null");
+  VGGTX_TRY(check_prec(prec));
+  if (total_frames < 0 || P <= 0) return fail(VGGTX_E_INVALID, "frames %d, P %d", total_frames, P);
+  *bytes = carve(h->cfg, agg_shape(h->cfg, total_frames, P), prec, nullptr).total;
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_aggregate(vggtx_handle h, const float* tokens, int S, int P, const vggtx_pair_w* w, int depth,
+                             const int32_t* out_layers, int n_out, void* out, vggtx_dtype out_dtype, vggtx_prec prec,
+                             void* ws, size_t ws_bytes, void* stream) {
+  if (S < 0) return fail(VGGTX_E_INVALID, "S = %d", S);
+  const int32_t off[2] = {0, S};
+  return aggregate_impl(h, tokens, off, 1, P, w, depth, out_layers, n_out, out, out_dtype, prec, ws, ws_bytes, stream);
+}
+
+vggtx_status vggtx_aggregate_varlen(vggtx_handle h, const float* tokens, const int32_t* frame_offsets, int n_scenes,
+                                    int P, const vggtx_pair_w* w, int depth, const int32_t* out_layers, int n_out,
+                                    void* out, vggtx_dtype out_dtype, vggtx_prec prec, void* ws, size_t ws_bytes,
+                                    void* stream) {
+  return aggregate_impl(h, tokens, frame_offsets, n_scenes, P, w, depth, out_layers, n_out, out, out_dtype, prec, ws,
+                        ws_bytes, stream);
+}
+
+vggtx_status vggtx_block(vggtx_handle h, const float* x_in, float* x_out, const int32_t* seq_offsets, int n_seq,
+                         const vggtx_block_w* w, vggtx_prec prec, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  VGGTX_TRY(check_prec(prec));
+  VGGTX_TRY(check_offsets(seq_offsets, n_seq, "sequence"));
+  if (!w) return fail(VGGTX_E_INVALID, "weights are null");
+  VGGTX_TRY(check_block_w(*w, "", 0));
+  const vggtx_config& c = h->cfg;
+  const int64_t N = seq_offsets[n_seq];
+  if (N > kMaxTokens) return fail(VGGTX_E_UNSUPPORTED, "too many tokens");
+  if (N == 0) return VGGTX_OK;
+  if (!x_in || !x_out) return fail(VGGTX_E_INVALID, "x_in / x_out is null");
+  if ((uintptr_t)x_in % 16 || (uintptr_t)x_out % 16) return fail(VGGTX_E_INVALID, "x must be 16-byte aligned");
+  int lmax = 0;
+  for (int i = 0; i < n_seq; ++i) lmax = std::max(lmax, seq_offsets[i + 1] - seq_offsets[i]);
+  const WsShape sh = agg_shape(c, n_seq, lmax);
+  const Ws need = carve(c, sh, prec, nullptr, false);
+  if (!ws || ws_bytes < need.total)
+    return fail(VGGTX_E_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need.total);
+  if ((uintptr_t)ws % 256) return fail(VGGTX_E_INVALID, "workspace must be 256-byte aligned");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+  BlockRun br;
+  br.ctx = h;
+  br.prec = prec;
+  br.ws = carve(c, sh, prec, (char*)ws, false);
+  br.ws.x = x_out;
+  br.N = N;
+  br.stream = (hipStream_t)stream;
+  VGGTX_HIP(launch_copy_f32(x_in, x_out, N * c.dim, br.stream));
+  const Seqs s = seqs_from_offsets(seq_offsets, n_seq, 1);
+  const int64_t chunk_rows = std::max<int64_t>(1, std::min<int64_t>(N, (int64_t)c.frame_chunk * std::max(1, lmax)));
+  return block_global(br, *w, s, chunk_rows, prec == VGGTX_FP8_E4M3, sh.npad, sh.nblk, nullptr, 0, false);
+}
+
+vggtx_status vggtx_attn_workspace_size(vggtx_handle h, const int32_t* seq_offsets, int n_seq, int H, int D,
+                                       vggtx_prec prec, size_t* bytes) {
+  if (!h || !bytes) return fail(VGGTX_E_INVALID, "handle / bytes is null");
+  VGGTX_TRY(check_prec(prec));
+  VGGTX_TRY(check_offsets(seq_offsets, n_seq, "sequence"));
+  if (D != kHeadDim) return fail(VGGTX_E_UNSUPPORTED, "head dim %d: only 64 is supported", D);
+  if (H <= 0) return fail(VGGTX_E_INVALID, "H = %d", H);
+  const Seqs s = seqs_from_offsets(seq_offsets, n_seq, 1);
+  *bytes = carve_attn(H, seq_offsets[n_seq], s.padded_cols(), s.scale_blocks(), prec, nullptr).total;
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_attn_frame(vggtx_handle h, const void* q, const void* k, const void* v, void* o, int S, int P, int H,
+                              int D, vggtx_layout in_layout, vggtx_layout out_layout, vggtx_prec prec, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (prec == VGGTX_FP8_E4M3) return fail(VGGTX_E_UNSUPPORTED, "frame attention runs in float32 or bfloat16");
+  if (S < 0 || P < 0) return fail(VGGTX_E_INVALID, "S = %d, P = %d", S, P);
+  Seqs s;
+  s.uniform = true; s.first = 0; s.len = P; s.n = (P > 0) ? S : 0; s.first_index = 0;
+  return attn_entry(h, VGGTX_K_ATTN_FRAME, q, k, v, o, s, H, D, in_layout, out_layout, prec, ws, ws_bytes, stream);
+}
+
+vggtx_status vggtx_attn_global(vggtx_handle h, const void* q, const void* k, const void* v, void* o,
+                               const int32_t* seq_offsets, int n_seq, int H, int D, vggtx_layout in_layout,
+                               vggtx_layout out_layout, vggtx_prec prec, void* ws, size_t ws_bytes, void* stream) {
+  VGGTX_TRY(check_offsets(seq_offsets, n_seq, "sequence"));
+  const Seqs s = seqs_from_offsets(seq_offsets, n_seq, 1);
+  return attn_entry(h, VGGTX_K_ATTN_GLOBAL, q, k, v, o, s, H, D, in_layout, out_layout, prec, ws, ws_bytes, stream);
+}
+
+vggtx_status vggtx_quantize_fp8(vggtx_handle h, const void* x, vggtx_layout in_layout, const int32_t* seq_offsets,
+                                int n_seq, int H, int D, uint8_t* codes, float* scales, void* stream) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  VGGTX_TRY(check_offsets(seq_offsets, n_seq, "sequence"));
+  if (D != kHeadDim) return fail(VGGTX_E_UNSUPPORTED, "head dim %d: only 64 is supported", D);
+  if (H <= 0) return fail(VGGTX_E_INVALID, "H = %d", H);
+  VGGTX_TRY(check_layout(in_layout, H, "input"));
+  const int64_t N = seq_offsets[n_seq];
+  if (N > kMaxTokens) return fail(VGGTX_E_UNSUPPORTED, "too many tokens");
+  if (N == 0) return VGGTX_OK;
+  if (!x || !codes || !scales) return fail(VGGTX_E_INVALID, "x / codes / scales is null");
+  if ((uintptr_t)x % 16 || (uintptr_t)codes % 16) return fail(VGGTX_E_INVALID, "x / codes must be 16-byte aligned");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+  const Seqs s = seqs_from_offsets(seq_offsets, n_seq, 1);
+  const int64_t nblk = s.scale_blocks();
+  for (auto& tn : make_tables(s, kQuantRows))
+    VGGTX_HIP(launch_quant_fp8((const bf16*)x, in_layout.token_stride, in_layout.head_stride, codes, N * kHeadDim, 0,
+                               false, scales, nblk, tn.first, tn.second, H, (hipStream_t)stream));
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_timing_enable(vggtx_handle h, int enable) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+  KernelTimer& t = h->timer;
+  if (enable && t.ev.empty()) {
+    t.ev.resize(2 * KernelTimer::kMaxRec);
+    for (auto& e : t.ev) VGGTX_HIP(hipEventCreate(&e));
+  }
+  t.enabled = enable != 0;
+  t.cls.clear();
+  t.flops.clear();
+  t.dropped = 0;
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_timing_read(vggtx_handle h, vggtx_timing out[VGGTX_K_COUNT], int64_t* dropped) {
+  if (!h || !out) return fail(VGGTX_E_INVALID, "handle / out is null");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+  KernelTimer& t = h->timer;
+  for (int k = 0; k < VGGTX_K_COUNT; ++k) out[k] = vggtx_timing{0.0, 0, 0.0};
+  for (size_t i = 0; i < t.cls.size(); ++i) {
+    VGGTX_HIP(hipEventSynchronize(t.ev[2 * i + 1]));
+    float ms = 0.f;
+    VGGTX_HIP(hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]));
+    out[t.cls[i]].total_ms += ms;
+    out[t.cls[i]].launches += 1;
+    out[t.cls[i]].flops += t.flops[i];
+  }
+  if (dropped) *dropped = t.dropped;
+  t.cls.clear();
+  t.flops.clear();
+  t.dropped = 0;
+  return VGGTX_OK;
+}
+
+const char* vggtx_status_str(vggtx_status s) {
+  switch (s) {
+    case VGGTX_OK: return "ok";
+    case VGGTX_E_INVALID: return "invalid argument";
+    case VGGTX_E_UNSUPPORTED: return "unsupported";
+    case VGGTX_E_WORKSPACE: return "workspace too small";
+    case VGGTX_E_HIP: return "HIP error";
+    case VGGTX_E_NODEVICE: return "no device";
+  }
+  return "unknown status";
+}
+
+const char* vggtx_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,282 @@
+"""Thin ctypes binding of the vggtx C-ABI (include/vggtx.h).
+
+Argument marshalling only: every step of the aggregator runs in the HIP
+library.  PyTorch provides device memory and the current stream.  Function
+names follow the C entry points without the ``vggtx_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence
+
+import torch
+
+__all__ = [
+    "F32", "BF16", "FP8_E4M3", "OUT_F32", "OUT_BF16", "VggtxError", "library_path", "load",
+    "Config", "BlockW", "PairW", "Layout", "Handle", "create", "destroy", "workspace_size",
+    "aggregate", "aggregate_varlen", "block", "attn_workspace_size", "attn_frame", "attn_global",
+    "quantize_fp8", "status_str", "last_error", "BLOCK_FIELDS", "timing_enable", "timing_read",
+    "K_ATTN_GLOBAL", "K_ATTN_FRAME", "K_GEMM", "K_OTHER",
+]
+
+F32, BF16, FP8_E4M3 = 0, 1, 2
+K_ATTN_GLOBAL, K_ATTN_FRAME, K_GEMM, K_OTHER = 0, 1, 2, 3
+OUT_F32, OUT_BF16 = 0, 1
+BLOCK_FIELDS = ("ln1_g", "ln1_b", "w_qkv", "b_qkv", "w_o", "b_o",
+                "ln2_g", "ln2_b", "w_fc1", "b_fc1", "w_fc2", "b_fc2")
+
+_LIB_NAME = "libvggtx.so"
+_lib = None
+
+
+def library_path() -> str:
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), _LIB_NAME)
+
+
+class VggtxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"vggtx status {status} ({status_str(status)}): {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("heads", ctypes.c_int), ("head_dim", ctypes.c_int),
+                ("mlp_hidden", ctypes.c_int), ("ln_eps", ctypes.c_float), ("frame_chunk", ctypes.c_int)]
+
+
+class BlockW(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in BLOCK_FIELDS]
+
+
+class PairW(ctypes.Structure):
+    _fields_ = [("frame", BlockW), ("global_", BlockW)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("token_stride", ctypes.c_int64), ("head_stride", ctypes.c_int64)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("total_ms", ctypes.c_double), ("launches", ctypes.c_int64), ("flops", ctypes.c_double)]
+
+
+def load():
+    """Load libvggtx.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2509_25191_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    P_i32 = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "vggtx_create": [ctypes.POINTER(vp), i32, ctypes.POINTER(Config)],
+        "vggtx_destroy": [vp],
+        "vggtx_workspace_size": [vp, i32, i32, i32, ctypes.POINTER(sz)],
+        "vggtx_aggregate": [vp, vp, i32, i32, ctypes.POINTER(PairW), i32, P_i32, i32, vp, i32, i32, vp, sz, vp],
+        "vggtx_aggregate_varlen": [vp, vp, P_i32, i32, i32, ctypes.POINTER(PairW), i32, P_i32, i32, vp, i32, i32,
+                                   vp, sz, vp],
+        "vggtx_block": [vp, vp, vp, P_i32, i32, ctypes.POINTER(BlockW), i32, vp, sz, vp],
+        "vggtx_attn_workspace_size": [vp, P_i32, i32, i32, i32, i32, ctypes.POINTER(sz)],
+        "vggtx_attn_frame": [vp, vp, vp, vp, vp, i32, i32, i32, i32, Layout, Layout, i32, vp, sz, vp],
+        "vggtx_attn_global": [vp, vp, vp, vp, vp, P_i32, i32, i32, i32, Layout, Layout, i32, vp, sz, vp],
+        "vggtx_quantize_fp8": [vp, vp, Layout, P_i32, i32, i32, i32, vp, vp, vp],
+        "vggtx_timing_enable": [vp, i32],
+        "vggtx_timing_read": [vp, ctypes.POINTER(Timing), ctypes.POINTER(ctypes.c_int64)],
+        "vggtx_status_str": [i32],
+        "vggtx_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name in ("vggtx_status_str", "vggtx_last_error") else ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_str(s: int) -> str:
+    return load().vggtx_status_str(int(s)).decode()
+
+
+def last_error() -> str:
+    return load().vggtx_last_error().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise VggtxError(status, last_error())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        stream = stream.cuda_stream
+    return ctypes.c_void_p(int(stream))
+
+
+def _i32_array(vals: Sequence[int]):
+    arr = (ctypes.c_int32 * max(1, len(vals)))(*[int(v) for v in vals])
+    return arr
+
+
+def create(device: int, dim: int, heads: int, head_dim: int = 64, mlp_hidden: Optional[int] = None,
+           ln_eps: float = 1e-6, frame_chunk: int = 128) -> ctypes.c_void_p:
+    cfg = Config(dim, heads, head_dim, mlp_hidden if mlp_hidden is not None else 4 * dim, ln_eps, frame_chunk)
+    h = ctypes.c_void_p()
+    _check(load().vggtx_create(ctypes.byref(h), int(device), ctypes.byref(cfg)))
+    return h
+
+
+def destroy(h) -> None:
+    _check(load().vggtx_destroy(h))
+
+
+def workspace_size(h, total_frames: int, P: int, prec: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load().vggtx_workspace_size(h, int(total_frames), int(P), int(prec), ctypes.byref(n)))
+    return n.value
+
+
+def block_w(params: Dict[str, torch.Tensor]) -> BlockW:
+    return BlockW(*[ctypes.c_void_p(params[n].data_ptr()) for n in BLOCK_FIELDS])
+
+
+def pair_array(layers: List[Dict[str, Dict[str, torch.Tensor]]]):
+    arr = (PairW * len(layers))()
+    for i, l in enumerate(layers):
+        arr[i].frame = block_w(l["frame"])
+        arr[i].global_ = block_w(l["global"])
+    return arr
+
+
+def _alloc_ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def aggregate(h, tokens: torch.Tensor, layers, out_layers: Sequence[int], prec: int, out: Optional[torch.Tensor] = None,
+              out_dtype: int = OUT_BF16, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """tokens [S, P, C] float32 on the device; layers: list of {"frame": {...}, "global": {...}}."""
+    S, P, C = tokens.shape
+    return aggregate_varlen(h, tokens, [0, S], layers, out_layers, prec, out, out_dtype, ws, stream, _single=True)
+
+
+def aggregate_varlen(h, tokens: torch.Tensor, frame_offsets: Sequence[int], layers, out_layers: Sequence[int],
+                     prec: int, out: Optional[torch.Tensor] = None, out_dtype: int = OUT_BF16,
+                     ws: Optional[torch.Tensor] = None, stream=None, _single: bool = False) -> torch.Tensor:
+    S, P, C = tokens.shape
+    if out is None:
+        out = torch.empty((len(out_layers), S, P, 2 * C), device=tokens.device,
+                          dtype=torch.float32 if out_dtype == OUT_F32 else torch.bfloat16)
+    if ws is None:
+        ws = _alloc_ws(workspace_size(h, S, P, prec), tokens.device)
+    pw = pair_array(layers)
+    ol = _i32_array(out_layers)
+    if _single:
+        st = load().vggtx_aggregate(h, _ptr(tokens), S, P, pw, len(layers), ol, len(out_layers), _ptr(out),
+                                    out_dtype, prec, _ptr(ws), ws.numel(), _stream(stream))
+    else:
+        fo = _i32_array(frame_offsets)
+        st = load().vggtx_aggregate_varlen(h, _ptr(tokens), fo, len(frame_offsets) - 1, P, pw, len(layers), ol,
+                                           len(out_layers), _ptr(out), out_dtype, prec, _ptr(ws), ws.numel(),
+                                           _stream(stream))
+    _check(st)
+    return out
+
+
+def block(h, x_in: torch.Tensor, x_out: torch.Tensor, seq_offsets: Sequence[int], params: Dict[str, torch.Tensor],
+          prec: int, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    if ws is None:
+        lmax = max(b - a for a, b in zip(seq_offsets[:-1], seq_offsets[1:])) if len(seq_offsets) > 1 else 1
+        ws = _alloc_ws(workspace_size(h, len(seq_offsets) - 1, max(1, lmax), prec), x_in.device)
+    bw = block_w(params)
+    _check(load().vggtx_block(h, _ptr(x_in), _ptr(x_out), _i32_array(seq_offsets), len(seq_offsets) - 1,
+                              ctypes.byref(bw), prec, _ptr(ws), ws.numel(), _stream(stream)))
+    return x_out
+
+
+def attn_workspace_size(h, seq_offsets: Sequence[int], H: int, D: int, prec: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load().vggtx_attn_workspace_size(h, _i32_array(seq_offsets), len(seq_offsets) - 1, H, D, prec,
+                                            ctypes.byref(n)))
+    return n.value
+
+
+def _layout(t: torch.Tensor) -> Layout:
+    # t viewed as [tokens, H, D]
+    return Layout(t.stride(0), t.stride(1))
+
+
+def attn_frame(h, q, k, v, o, S: int, P: int, prec: int, ws: Optional[torch.Tensor] = None, stream=None):
+    """q, k, v, o: [S*P, H, D] views (any token / head strides, unit stride along D)."""
+    H, D = q.shape[1], q.shape[2]
+    if ws is None:
+        ws = _alloc_ws(attn_workspace_size(h, [f * P for f in range(S + 1)], H, D, prec), q.device)
+    _check(load().vggtx_attn_frame(h, _ptr(q), _ptr(k), _ptr(v), _ptr(o), S, P, H, D, _layout(q), _layout(o), prec,
+                                   _ptr(ws), ws.numel(), _stream(stream)))
+    return o
+
+
+def attn_global(h, q, k, v, o, seq_offsets: Sequence[int], prec: int, ws: Optional[torch.Tensor] = None,
+                stream=None):
+    H, D = q.shape[1], q.shape[2]
+    if ws is None:
+        ws = _alloc_ws(attn_workspace_size(h, seq_offsets, H, D, prec), q.device)
+    _check(load().vggtx_attn_global(h, _ptr(q), _ptr(k), _ptr(v), _ptr(o), _i32_array(seq_offsets),
+                                    len(seq_offsets) - 1, H, D, _layout(q), _layout(o), prec, _ptr(ws), ws.numel(),
+                                    _stream(stream)))
+    return o
+
+
+def quantize_fp8(h, x, seq_offsets: Sequence[int], codes=None, scales=None, stream=None):
+    """x [N, H, D] bfloat16 -> codes uint8 [H, N, D], scales float32 [H, n_blocks]."""
+    N, H, D = x.shape
+    nblk = sum((b - a + 127) // 128 for a, b in zip(seq_offsets[:-1], seq_offsets[1:]))
+    if codes is None:
+        codes = torch.empty((H, N, D), dtype=torch.uint8, device=x.device)
+    if scales is None:
+        scales = torch.empty((H, max(1, nblk)), dtype=torch.float32, device=x.device)
+    _check(load().vggtx_quantize_fp8(h, _ptr(x), _layout(x), _i32_array(seq_offsets), len(seq_offsets) - 1, H, D,
+                                     _ptr(codes), _ptr(scales), _stream(stream)))
+    return codes, scales
+
+
+def timing_enable(h, enable: bool = True) -> None:
+    _check(load().vggtx_timing_enable(h, 1 if enable else 0))
+
+
+def timing_read(h) -> dict:
+    """{class: {"ms", "launches", "flops"}} since the last enable/read, plus "dropped"."""
+    arr = (Timing * 4)()
+    dropped = ctypes.c_int64()
+    _check(load().vggtx_timing_read(h, arr, ctypes.byref(dropped)))
+    names = {K_ATTN_GLOBAL: "attn_global", K_ATTN_FRAME: "attn_frame", K_GEMM: "gemm", K_OTHER: "other"}
+    out = {names[i]: {"ms": arr[i].total_ms, "launches": arr[i].launches, "flops": arr[i].flops} for i in range(4)}
+    out["dropped"] = dropped.value
+    return out
+
+
+class Handle:
+    """Owns a vggtx handle for one device and model shape."""
+
+    def __init__(self, device: int = 0, dim: int = 1024, heads: int = 16, head_dim: int = 64,
+                 mlp_hidden: Optional[int] = None, ln_eps: float = 1e-6, frame_chunk: int = 128):
+        self.h = create(device, dim, heads, head_dim, mlp_hidden, ln_eps, frame_chunk)
+
+    def close(self):
+        if self.h is not None:
+            destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,139 @@
+"""Parity of the HIP block / aggregator with the FP64 oracle, and the
+invariants the paper states for the memory-efficient aggregator (Sec. 3.2):
+chunking and dropping unused layer outputs change nothing, frame-wise work is
+intra-frame, scenes are independent."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import DEV, max_abs_rel, to_dev, weights_to_dev
+
+vg = pytest.importorskip("paper_2509_25191_amd.vggtx")
+pytestmark = pytest.mark.gpu
+
+SMALL = synth.ModelConfig(dim=256, heads=4, head_dim=64, mlp_hidden=1024, depth=1)
+
+
+def _handle(m, chunk=128):
+    return vg.Handle(0, dim=m.dim, heads=m.heads, head_dim=m.head_dim, mlp_hidden=m.mlp_hidden,
+                     ln_eps=m.ln_eps, frame_chunk=chunk)
+
+
+def _dt(prec):
+    return torch.float32 if prec == vg.F32 else torch.bfloat16
+
+
+@pytest.mark.parametrize("prec,tol", [(vg.F32, 1e-4), (vg.BF16, 2e-2), (vg.FP8_E4M3, 6e-2)])
+@pytest.mark.parametrize("std", [0.02, 0.15])
+def test_block_parity(prec, tol, std):
+    m = SMALL
+    rng = np.random.default_rng(11)
+    w = synth.gen_block(rng, m.dim, m.mlp_hidden, std=std, bf16=prec != vg.F32)
+    offs = [0, 86, 172, 300]
+    x = rng.standard_normal((offs[-1], m.dim)).astype(np.float32)
+    ref = oracle.block(x, w, list(zip(offs[:-1], offs[1:])), m.heads, m.ln_eps)
+    h = _handle(m)
+    xd = to_dev(x, torch.float32)
+    yd = torch.empty_like(xd)
+    vg.block(h.h, xd, yd, offs, {k: to_dev(v, _dt(prec)) for k, v in w.items()}, prec)
+    torch.cuda.synchronize()
+    got = yd.cpu().numpy()
+    # the residual dominates the output; also gate the block's increment y - x
+    e = max_abs_rel(got, ref)
+    ei = max_abs_rel(got - x, ref - x)
+    print(f"block prec={prec} std={std} out={e:.3e} increment={ei:.3e}")
+    assert e < tol
+
+
+@pytest.mark.parametrize("prec,tol,out_dtype", [(vg.F32, 1e-4, vg.OUT_F32), (vg.BF16, 2e-2, vg.OUT_BF16),
+                                                (vg.BF16, 2e-2, vg.OUT_F32), (vg.FP8_E4M3, 6e-2, vg.OUT_BF16)])
+def test_aggregate_one_pair_s8(prec, tol, out_dtype):
+    """One frame/global pair, C=256, S=8 frames of P=86 tokens, seed 0."""
+    m = SMALL
+    S, P = 8, 86
+    tokens, layers = synth.gen_problem(m, S, P, seed=0, bf16=prec != vg.F32)
+    ref = oracle.aggregate(tokens, layers, [0], m.heads, m.ln_eps)
+    h = _handle(m)
+    out = vg.aggregate(h.h, to_dev(tokens, torch.float32), weights_to_dev(layers, _dt(prec)), [0], prec,
+                       out_dtype=out_dtype)
+    torch.cuda.synchronize()
+    got = out.float().cpu().numpy()
+    ef = max_abs_rel(got[..., :m.dim], ref[..., :m.dim])
+    eg = max_abs_rel(got[..., m.dim:], ref[..., m.dim:])
+    print(f"aggregate s8 prec={prec} out={out_dtype} frame_half={ef:.3e} global_half={eg:.3e}")
+    assert ef < tol and eg < tol
+
+
+def _run(h, tokens, layers, out_layers, prec=vg.BF16, offsets=None):
+    td = to_dev(tokens, torch.float32)
+    if offsets is None:
+        out = vg.aggregate(h.h, td, layers, out_layers, prec)
+    else:
+        out = vg.aggregate_varlen(h.h, td, offsets, layers, out_layers, prec)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_chunking_is_bitwise_invariant():
+    m = synth.ModelConfig(dim=128, heads=2, head_dim=64, mlp_hidden=256, depth=2)
+    S, P = 7, 37
+    tokens, layers = synth.gen_problem(m, S, P, seed=1, bf16=True)
+    ld = weights_to_dev(layers, torch.bfloat16)
+    outs = [_run(_handle(m, chunk), tokens, ld, [0, 1]) for chunk in (1, 3, 7, 128)]
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+def test_out_layer_subset_is_bitwise_slice():
+    m = synth.ModelConfig(dim=128, heads=2, head_dim=64, mlp_hidden=256, depth=3)
+    tokens, layers = synth.gen_problem(m, 3, 50, seed=2, bf16=True)
+    ld = weights_to_dev(layers, torch.bfloat16)
+    h = _handle(m)
+    full = _run(h, tokens, ld, [0, 1, 2])
+    sub = _run(h, tokens, ld, [1])
+    assert torch.equal(sub[0], full[1])
+
+
+def test_frame_block_is_intra_frame():
+    m = synth.ModelConfig(dim=128, heads=2, head_dim=64, mlp_hidden=256, depth=1)
+    S, P = 4, 40
+    tokens, layers = synth.gen_problem(m, S, P, seed=3, bf16=True)
+    ld = weights_to_dev(layers, torch.bfloat16)
+    h = _handle(m, chunk=2)
+    a = _run(h, tokens, ld, [0])
+    t2 = tokens.copy(); t2[2] += 1.0
+    b = _run(h, t2, ld, [0])
+    C = m.dim
+    for f in (0, 1, 3):
+        assert torch.equal(a[0, f, :, :C], b[0, f, :, :C])
+    assert not torch.equal(a[0, 2, :, :C], b[0, 2, :, :C])
+
+
+def test_varlen_equals_each_scene_alone():
+    m = synth.ModelConfig(dim=128, heads=2, head_dim=64, mlp_hidden=256, depth=2)
+    P = 45
+    scenes = [3, 1, 0, 5]
+    offs = np.concatenate([[0], np.cumsum(scenes)]).tolist()
+    tokens, layers = synth.gen_problem(m, sum(scenes), P, seed=4, bf16=True)
+    ld = weights_to_dev(layers, torch.bfloat16)
+    h = _handle(m)
+    both = _run(h, tokens, ld, [0, 1], offsets=offs)
+    for a, b in zip(offs[:-1], offs[1:]):
+        if b > a:
+            alone = _run(h, tokens[a:b], ld, [0, 1])
+            assert torch.equal(both[:, a:b], alone)
+    ref = oracle.aggregate(tokens, layers, [0, 1], m.heads, m.ln_eps, scene_frames=scenes)
+    assert max_abs_rel(both.float().cpu().numpy(), ref) < 2e-2
+
+
+def test_run_twice_is_deterministic():
+    m = synth.ModelConfig(dim=128, heads=2, head_dim=64, mlp_hidden=256, depth=1)
+    tokens, layers = synth.gen_problem(m, 5, 70, seed=5, bf16=True)
+    ld = weights_to_dev(layers, torch.bfloat16)
+    h = _handle(m)
+    for prec in (vg.BF16, vg.FP8_E4M3):
+        a = _run(h, tokens, ld, [0], prec=prec)
+        b = _run(h, tokens, ld, [0], prec=prec)
+        assert torch.equal(a, b)

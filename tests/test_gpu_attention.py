@@ -1,0 +1,150 @@
+"""Parity of the HIP attention kernels and the FP8 quantiser with the FP64 oracle.
+
+Attention outputs are compared head by head, element by element, in three
+logit regimes (random-init, logit std ~3, peaked multi-view-like)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import DEV, max_abs_rel, to_dev, head_major_to_tokens
+
+vg = pytest.importorskip("paper_2509_25191_amd.vggtx")
+pytestmark = pytest.mark.gpu
+
+TOL = {vg.F32: 1e-4, vg.BF16: 2e-2, vg.FP8_E4M3: 6e-2}
+
+
+@pytest.fixture(scope="module")
+def handle():
+    h = vg.Handle(0, dim=256, heads=4, mlp_hidden=1024)
+    yield h.h
+    h.close()
+
+
+def _qkv(H, N, D, regime, seed, frames=1, bf16=True):
+    rng = np.random.default_rng(seed)
+    return synth.gen_qkv(rng, H, N, D, regime, frames=frames, bf16=bf16)
+
+
+def _dev_tokens(a, prec):
+    return to_dev(head_major_to_tokens(a), torch.float32 if prec == vg.F32 else torch.bfloat16)
+
+
+def _oracle_seqs(q, k, v, offs, rows=None):
+    out = np.zeros(q.shape)
+    for a, b in zip(offs[:-1], offs[1:]):
+        if b > a:
+            out[:, a:b] = oracle.attention(q[:, a:b], k[:, a:b], v[:, a:b])
+    return out
+
+
+def _run_global(handle, q, k, v, offs, prec):
+    H, N, D = q.shape
+    qd, kd, vd = (_dev_tokens(a, prec) for a in (q, k, v))
+    o = torch.zeros_like(qd)
+    vg.attn_global(handle, qd, kd, vd, o, offs, prec)
+    torch.cuda.synchronize()
+    return o.float().cpu().numpy().transpose(1, 0, 2)
+
+
+@pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3])
+@pytest.mark.parametrize("regime", ["R0", "R1", "R2"])
+def test_attn_global_small(handle, prec, regime):
+    H, S, P, D = 4, 8, 86, 64
+    q, k, v = _qkv(H, S * P, D, regime, seed=1, frames=S, bf16=prec != vg.F32)
+    got = _run_global(handle, q, k, v, [0, S * P], prec)
+    ref = _oracle_seqs(q, k, v, [0, S * P])
+    e = max_abs_rel(got, ref)
+    print(f"attn_global prec={prec} regime={regime} max_abs_rel={e:.3e}")
+    tol = TOL[prec] if not (prec == vg.FP8_E4M3 and regime == "R2") else 1.5e-1
+    assert e < tol
+
+
+@pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3])
+def test_attn_global_varlen_ragged(handle, prec):
+    H, D = 4, 64
+    offs = [0, 200, 201, 201, 718, 845]  # includes a 1-token and an empty sequence
+    q, k, v = _qkv(H, offs[-1], D, "R1", seed=2, bf16=prec != vg.F32)
+    got = _run_global(handle, q, k, v, offs, prec)
+    ref = _oracle_seqs(q, k, v, offs)
+    e = max_abs_rel(got, ref)
+    print(f"varlen prec={prec} max_abs_rel={e:.3e}")
+    assert e < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [vg.F32, vg.BF16])
+@pytest.mark.parametrize("S,P", [(8, 86), (3, 1374), (5, 1)])
+def test_attn_frame(handle, prec, S, P):
+    H, D = 4, 64
+    q, k, v = _qkv(H, S * P, D, "R1", seed=3, bf16=prec != vg.F32)
+    qd, kd, vd = (_dev_tokens(a, prec) for a in (q, k, v))
+    o = torch.zeros_like(qd)
+    vg.attn_frame(handle, qd, kd, vd, o, S, P, prec)
+    torch.cuda.synchronize()
+    got = o.float().cpu().numpy().transpose(1, 0, 2)
+    ref = _oracle_seqs(q, k, v, [f * P for f in range(S + 1)])
+    e = max_abs_rel(got, ref)
+    print(f"attn_frame prec={prec} S={S} P={P} max_abs_rel={e:.3e}")
+    assert e < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [vg.F32, vg.BF16])
+def test_global_equals_frame_for_one_frame(handle, prec):
+    H, P, D = 4, 300, 64
+    q, k, v = _qkv(H, P, D, "R1", seed=4, bf16=prec != vg.F32)
+    qd, kd, vd = (_dev_tokens(a, prec) for a in (q, k, v))
+    o1 = torch.zeros_like(qd); o2 = torch.zeros_like(qd)
+    vg.attn_frame(handle, qd, kd, vd, o1, 1, P, prec)
+    vg.attn_global(handle, qd, kd, vd, o2, [0, P], prec)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, o2)
+
+
+def test_attn_global_strided_layouts(handle):
+    """q/k/v as slices of a packed [N, 3, H, D] tensor and O into a [N, H*D] buffer."""
+    H, N, D = 4, 517, 64
+    q, k, v = _qkv(H, N, D, "R1", seed=5)
+    packed = torch.zeros((N, 3, H, D), dtype=torch.bfloat16, device=DEV)
+    for i, a in enumerate((q, k, v)):
+        packed[:, i] = to_dev(head_major_to_tokens(a), torch.bfloat16)
+    o = torch.zeros((N, H * D), dtype=torch.bfloat16, device=DEV)
+    vg.attn_global(handle, packed[:, 0], packed[:, 1], packed[:, 2], o.view(N, H, D), [0, N], vg.BF16)
+    torch.cuda.synchronize()
+    got = o.float().cpu().numpy().reshape(N, H, D).transpose(1, 0, 2)
+    assert max_abs_rel(got, oracle.attention(q, k, v)) < 2e-2
+
+
+def test_attn_global_sampled_rows_large(handle):
+    """N = 43,968 (32 frames of 1374 tokens); oracle on 256 sampled query rows."""
+    H, S, P, D = 2, 32, 1374, 64
+    N = S * P
+    q, k, v = _qkv(H, N, D, "R2", seed=6, frames=S)
+    got = _run_global(handle, q, k, v, [0, N], vg.BF16)
+    rows = synth.sample_rows(6, N, 256, P)
+    ref = oracle.attention(q[:, rows], k, v)
+    e = max_abs_rel(got[:, rows], ref)
+    print(f"large sampled max_abs_rel={e:.3e}")
+    assert e < 2e-2
+
+
+def test_quantize_fp8_bit_exact(handle):
+    H, D = 4, 64
+    offs = [0, 300, 301, 688]
+    rng = np.random.default_rng(7)
+    x = synth.round_bf16(rng.normal(0, 0.8, (offs[-1], H, D)).astype(np.float32))
+    x[5:9, 1] *= 40.0  # a block with a large amax
+    x[300, :] = 0.0    # the one-token sequence is all zero: scale 1, codes 0
+    xd = to_dev(x, torch.bfloat16)
+    codes, scales = vg.quantize_fp8(handle, xd, offs)
+    torch.cuda.synchronize()
+    codes = codes.cpu().numpy(); scales = scales.cpu().numpy()
+    blk = 0
+    for a, b in zip(offs[:-1], offs[1:]):
+        starts = np.arange(a, b, 128); ends = np.minimum(starts + 128, b)
+        for h in range(H):
+            rc, rs = oracle.quantize_rows(x[:, h], starts, ends)
+            np.testing.assert_array_equal(codes[h, a:b], rc[a:b])
+            np.testing.assert_array_equal(scales[h, blk:blk + len(starts)], rs)
+        blk += len(starts)
