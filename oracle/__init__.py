@@ -19,6 +19,8 @@ Parity status by function (what pins each one is listed in tests/test_oracle.py)
   invariants).
   e4m3_encode / e4m3_decode / quantize_rows: pinned (OCP FP8 definition,
   exhaustive code table, torch.float8_e4m3fn).
+  attention_fp8_emulated: pinned by invariants (constant V gives that row
+  exactly; error against the exact attention within the E4M3 bound).
   Agreement of the whole network with a trained VGGT: parity unpinned (no
   trained weights or worked numeric example exist for this path).
 """
@@ -27,4 +29,4 @@ from .aggregator import (  # noqa: F401
     attention_probs, block, aggregate, global_block_rows, frame_block_frames,
     frame_bounds, scene_bounds,
 )
-from .fp8 import e4m3_decode, e4m3_encode, quantize_rows, E4M3_MAX  # noqa: F401
+from .fp8 import e4m3_decode, e4m3_encode, quantize_rows, attention_fp8_emulated, E4M3_MAX  # noqa: F401

@@ -83,3 +83,34 @@ def quantize_rows(x: np.ndarray, block_starts: np.ndarray, block_ends: np.ndarra
         scales[i] = np.float32(amax / np.float32(E4M3_MAX))
         codes[a:e] = e4m3_encode((blk * inv).astype(np.float32).astype(np.float64))
     return codes, scales
+
+
+def attention_fp8_emulated(q: np.ndarray, k: np.ndarray, v: np.ndarray, block: int = 128) -> np.ndarray:
+    """What FP8 E4M3 global attention computes, emulated in float64 for one
+    sequence: q, k, v [H, n, D] are quantised per (head, 128-row block)
+    (``quantize_rows``); logits use the dequantised Q and K; the V block scale
+    is folded into the probabilities, A_j = p_j * 448 * s_v(b_j) / max_b s_v,
+    which are rounded to E4M3; the output is sum_j A_j V8_j / sum_j A_j / r_j
+    times max_b s_v / 448 (the row sum taken from the rounded A).  The
+    softmax here uses the final row maximum (two-pass); a streamed kernel
+    rounds against its running maximum instead, so the two differ by
+    rounding only.  Used to tell the error of the format from kernel error."""
+    q = np.asarray(q, np.float64); k = np.asarray(k, np.float64); v = np.asarray(v, np.float64)
+    H, n, D = q.shape
+    starts = np.arange(0, n, block); ends = np.minimum(starts + block, n)
+    rows = ends - starts
+    out = np.empty((H, n, D))
+    for h in range(H):
+        qc, qs = quantize_rows(q[h], starts, ends)
+        kc, ks = quantize_rows(k[h], starts, ends)
+        vc, vs = quantize_rows(v[h], starts, ends)
+        qd = e4m3_decode(qc) * np.repeat(qs, rows)[:, None]
+        kd = e4m3_decode(kc) * np.repeat(ks, rows)[:, None]
+        v8 = e4m3_decode(vc)
+        s = qd @ kd.T / np.sqrt(D)
+        p = np.exp(s - s.max(axis=1, keepdims=True))
+        vmax = vs.astype(np.float64).max()
+        r = E4M3_MAX * np.repeat(vs, rows).astype(np.float64) / vmax
+        a = e4m3_decode(e4m3_encode(p * r[None, :]))
+        out[h] = (a @ v8) * (vmax / E4M3_MAX) / (a / r[None, :]).sum(axis=1, keepdims=True)
+    return out

@@ -123,48 +123,46 @@ __global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
     const int kt = it.s0 + t * BN, buf = t & 1;
     if (t + 1 < ntiles) gload(kt + BN);
 
-    bf16x8 kf[2][4], vf[2][2][2];
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int r = kb * 32 + r32;
-        kf[kb][c] = *(const bf16x8*)&Ks[buf][r * D + (((2 * c + g) ^ (r & 7)) * 8)];
-      }
-#pragma unroll
-    for (int db = 0; db < 2; ++db)
+    // Phase 1: scores of every query block (K fragments live only here).
+    f32x16 s[QB][2];
+    {
+      bf16x8 kf[2][4];
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int d = db * 32 + r32;
-          vf[db][kb][h] = *(const bf16x8*)&Vs[buf][d * BN + (((2 * (2 * kb + h) + g) ^ (d & 7)) * 8)];
+        for (int c = 0; c < 4; ++c) {
+          const int r = kb * 32 + r32;
+          kf[kb][c] = *(const bf16x8*)&Ks[buf][r * D + (((2 * c + g) ^ (r & 7)) * 8)];
         }
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+          s[qb][kb] = f32x16{};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) s[qb][kb] = mfma_bf16(kf[kb][c], qf[qb][c], s[qb][kb]);
+        }
+    }
 
+    // Phase 2: online softmax; probabilities packed as bf16 PV operands.
     const bool tail = kt + BN > it.s1;
+    bf16x8 pb[QB][2][2];
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-      f32x16 s[2];
-#pragma unroll
-      for (int kb = 0; kb < 2; ++kb) {
-        s[kb] = f32x16{};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) s[kb] = mfma_bf16(kf[kb][c], qf[qb][c], s[kb]);
-      }
       if (tail) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             const int key = kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3);
-            if (key >= it.s1) s[kb][i] = -INFINITY;
+            if (key >= it.s1) s[qb][kb][i] = -INFINITY;
           }
       }
-      float mx = s[0][0];
+      float mx = s[qb][0][0];
 #pragma unroll
-      for (int i = 1; i < 16; ++i) mx = __builtin_fmaxf(mx, s[0][i]);
+      for (int i = 1; i < 16; ++i) mx = __builtin_fmaxf(mx, s[qb][0][i]);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) mx = __builtin_fmaxf(mx, s[1][i]);
+      for (int i = 0; i < 16; ++i) mx = __builtin_fmaxf(mx, s[qb][1][i]);
       mx = __builtin_fmaxf(mx, __shfl_xor(mx, 32));
       const float m_new = __builtin_fmaxf(m_run[qb], mx);
       if (__any(m_new > m_run[qb])) {
@@ -178,23 +176,38 @@ __global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
         m_run[qb] = m_new;
       }
       const float mc = m_new * c2;
-      bf16x8 pb[2][2];
       float ls = 0.f;
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          const float e = fast_exp2(__builtin_fmaf(s[kb][i], c2, -mc));
+          const float e = fast_exp2(__builtin_fmaf(s[qb][kb][i], c2, -mc));
           ls += e;
-          pb[kb][i >> 3][i & 7] = f2bf(e);
+          pb[qb][kb][i >> 3][i & 7] = f2bf(e);
         }
       l_run[qb] += ls;
+    }
+
+    // Phase 3: O^T += V^T P^T (V fragments live only here).
+    {
+      bf16x8 vf[2][2][2];
 #pragma unroll
       for (int db = 0; db < 2; ++db)
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-          for (int h = 0; h < 2; ++h) oacc[qb][db] = mfma_bf16(vf[db][kb][h], pb[kb][h], oacc[qb][db]);
+          for (int h = 0; h < 2; ++h) {
+            const int d = db * 32 + r32;
+            vf[db][kb][h] = *(const bf16x8*)&Vs[buf][d * BN + (((2 * (2 * kb + h) + g) ^ (d & 7)) * 8)];
+          }
+#pragma unroll
+      for (int qb = 0; qb < QB; ++qb)
+#pragma unroll
+        for (int db = 0; db < 2; ++db)
+#pragma unroll
+          for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) oacc[qb][db] = mfma_bf16(vf[db][kb][h], pb[qb][kb][h], oacc[qb][db]);
     }
 
     if (t + 1 < ntiles) lstore(buf ^ 1);

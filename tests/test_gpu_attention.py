@@ -58,8 +58,14 @@ def test_attn_global_small(handle, prec, regime):
     ref = _oracle_seqs(q, k, v, [0, S * P])
     e = max_abs_rel(got, ref)
     print(f"attn_global prec={prec} regime={regime} max_abs_rel={e:.3e}")
-    tol = TOL[prec] if not (prec == vg.FP8_E4M3 and regime == "R2") else 1.5e-1
-    assert e < tol
+    if prec == vg.FP8_E4M3 and regime != "R0":
+        # large logits: the E4M3 rounding of Q and K dominates (reported, not gated at 6e-2);
+        # the kernel must not add error beyond what the format itself costs
+        e_fmt = max_abs_rel(oracle.attention_fp8_emulated(q, k, v), ref)
+        print(f"   E4M3 format error (emulated) {e_fmt:.3e}")
+        assert e < 1.3 * e_fmt + 1e-2
+    else:
+        assert e < TOL[prec]
 
 
 @pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3])
@@ -71,7 +77,16 @@ def test_attn_global_varlen_ragged(handle, prec):
     ref = _oracle_seqs(q, k, v, offs)
     e = max_abs_rel(got, ref)
     print(f"varlen prec={prec} max_abs_rel={e:.3e}")
-    assert e < TOL[prec]
+    if prec == vg.FP8_E4M3:
+        emu = np.zeros(q.shape)
+        for a, b in zip(offs[:-1], offs[1:]):
+            if b > a:
+                emu[:, a:b] = oracle.attention_fp8_emulated(q[:, a:b], k[:, a:b], v[:, a:b])
+        e_fmt = max_abs_rel(emu, ref)
+        print(f"   E4M3 format error (emulated) {e_fmt:.3e}")
+        assert e < 1.3 * e_fmt + 1e-2
+    else:
+        assert e < TOL[prec]
 
 
 @pytest.mark.parametrize("prec", [vg.F32, vg.BF16])
@@ -136,6 +151,7 @@ def test_quantize_fp8_bit_exact(handle):
     x = synth.round_bf16(rng.normal(0, 0.8, (offs[-1], H, D)).astype(np.float32))
     x[5:9, 1] *= 40.0  # a block with a large amax
     x[300, :] = 0.0    # the one-token sequence is all zero: scale 1, codes 0
+    x = synth.round_bf16(x)  # the device holds bf16: give the oracle the same values
     xd = to_dev(x, torch.bfloat16)
     codes, scales = vg.quantize_fp8(handle, xd, offs)
     torch.cuda.synchronize()

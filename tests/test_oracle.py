@@ -355,3 +355,22 @@ def test_sample_rows_forced_members():
     rows = synth.sample_rows(0, 10000, 256, 1374)
     assert len(rows) == 256 and rows[0] == 0 and rows[-1] == 9999 and len(set(rows.tolist())) == 256
     assert (rows >= (10000 // 128) * 128).any()
+
+
+def test_fp8_emulation_constant_v_and_error_bound():
+    rng = _rng(13)
+    q, k = rng.normal(0, 0.7, (2, 300, 64)), rng.normal(0, 0.7, (2, 300, 64))
+    row = synth.round_bf16(rng.normal(0, 1, 64).astype(np.float32)).astype(np.float64)
+    # a constant V row quantises exactly only up to E4M3 rounding of each entry; the
+    # output must equal the dequantised row (convex combination of identical rows)
+    v = np.broadcast_to(row, (2, 300, 64)).copy()
+    o = oracle.attention_fp8_emulated(q, k, v)
+    st = np.array([0, 128, 256]); en = np.array([128, 256, 300])
+    c, s = oracle.quantize_rows(v[0], st, en)
+    deq = oracle.e4m3_decode(c[0]) * s[0]
+    np.testing.assert_allclose(o, np.broadcast_to(deq, o.shape), rtol=0, atol=1e-12)
+    # random operands: error against the exact definition stays within a few E4M3 half-ulps
+    v = rng.normal(0, 1, (2, 300, 64))
+    ref = oracle.attention(q, k, v)
+    err = np.abs(oracle.attention_fp8_emulated(q, k, v) - ref).max() / np.abs(ref).max()
+    assert 1e-3 < err < 0.1
