@@ -177,6 +177,17 @@ def main():
     for i in range(args.steps):
         vg.aggregate(h.h, tokens, layers, OUT_LAYERS, prec, out=out, ws=ws)
     e1.record()
+    # report each global-attention launch as it completes (the step runs for
+    # minutes at S=1000; these lines come from the finished launches)
+    seen = 0
+    total_ga = args.steps * (max(OUT_LAYERS) + 1)
+    while seen < total_ga:
+        _, _, ga_done = vg.timing_poll(h.h)
+        if ga_done > seen:
+            seen = ga_done
+            log(f"global attention launches finished: {seen}/{total_ga} ({time.perf_counter() - t0:.1f}s)")
+        else:
+            time.sleep(0.5)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sec = e0.elapsed_time(e1) * 1e-3

@@ -204,6 +204,10 @@ typedef struct {
 
 vggtx_status vggtx_timing_enable(vggtx_handle h, int enable);
 vggtx_status vggtx_timing_read(vggtx_handle h, vggtx_timing out[VGGTX_K_COUNT], int64_t* dropped);
+/* Non-blocking progress query: of the launches recorded since the last
+ * enable/read, how many have finished (in issue order) and how many of those
+ * were global-attention launches.  Does not wait and does not clear. */
+vggtx_status vggtx_timing_poll(vggtx_handle h, int64_t* finished, int64_t* recorded, int64_t* finished_attn_global);
 
 const char* vggtx_status_str(vggtx_status s);
 /* Message of the last failing call on this thread ("" if none). */

@@ -46,6 +46,13 @@ __device__ __forceinline__ Item resolve_item(const SeqTable& t, int item, int ro
   return it;
 }
 
+
+__device__ __forceinline__ float lane_swap_max(float v) {
+  // v_permlane32_swap exchanges the two 32-lane halves of the wave
+  auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __builtin_fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+
 // ============================================================== BF16 kernel
 //
 // LDS tiles (BN = 64 keys, D = 64), 16-byte granules XOR-swizzled with the row
@@ -348,6 +355,13 @@ __global__ __launch_bounds__(256, 1) void attn_f32_kernel(AttnParams p) {
 
 
 // ============================================================== FP8 kernel
+// E4M3 conversion of values known to lie in [0, 448 * (1 + 2^-20)]: the
+// folded probabilities below never exceed r_b <= 448 because the running
+// maximum is exact, so no clamp is needed before the hardware converter.
+__device__ __forceinline__ uint32_t cvt_e4m3x2_inrange(float a, float b) {
+  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
+}
+
 // Global attention on OCP E4M3 operands (MFMA 32x32x64 f8f6f4, one MFMA per
 // 32x32 score block since K = D = 64).  Q, K and V carry one float32 scale
 // per 128-row block of their sequence; the K-block and Q-block scales and
@@ -444,12 +458,15 @@ __global__ __launch_bounds__(256, 2) void attn_fp8_kernel(AttnParams p) {
         for (int i = 0; i < 16; ++i)
           if (kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) s[kb][i] = -INFINITY;
     }
-    float mx = s[0][0];
+    float m4[4];
 #pragma unroll
-    for (int i = 1; i < 16; ++i) mx = __builtin_fmaxf(mx, s[0][i]);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) mx = __builtin_fmaxf(mx, s[1][i]);
-    mx = __builtin_fmaxf(mx, __shfl_xor(mx, 32));
+    for (int j = 0; j < 4; ++j) {
+      const f32x16& sv = s[j >> 1];
+      const int o = (j & 1) * 8;
+      m4[j] = __builtin_fmaxf(__builtin_fmaxf(__builtin_fmaxf(sv[o], sv[o + 1]), __builtin_fmaxf(sv[o + 2], sv[o + 3])),
+                              __builtin_fmaxf(__builtin_fmaxf(sv[o + 4], sv[o + 5]), __builtin_fmaxf(sv[o + 6], sv[o + 7])));
+    }
+    const float mx = lane_swap_max(__builtin_fmaxf(__builtin_fmaxf(m4[0], m4[1]), __builtin_fmaxf(m4[2], m4[3])));
     const float m_new = __builtin_fmaxf(m_run, mx * sigma);
     if (__any(m_new > m_run)) {
       const float alpha = fast_exp2(m_run - m_new);
@@ -471,7 +488,7 @@ __global__ __launch_bounds__(256, 2) void attn_fp8_kernel(AttnParams p) {
         const float e1 = fast_exp2(__builtin_fmaf(s[kb][i + 1], sigma, -off));
         const float e2 = fast_exp2(__builtin_fmaf(s[kb][i + 2], sigma, -off));
         const float e3 = fast_exp2(__builtin_fmaf(s[kb][i + 3], sigma, -off));
-        pw[(16 * kb + i) >> 2] = (int)(cvt_e4m3x2(e0, e1) | (cvt_e4m3x2(e2, e3) << 16));
+        pw[(16 * kb + i) >> 2] = (int)(cvt_e4m3x2_inrange(e0, e1) | (cvt_e4m3x2_inrange(e2, e3) << 16));
       }
     const f32x16 lsum = mfma_fp8(ones8, pw, f32x16{});
     l_run = __builtin_fmaf(lsum[0], 1.f / rb, l_run);
@@ -611,10 +628,8 @@ __global__ void scale_max_kernel(const float* scales, int64_t sc_hs, int n_block
 }
 
 // ============================================================== launchers
-int attn_block_rows(int prec, int qb_per_wave) {
-  if (prec == 0) return 128;
-  if (prec == 2) return 128;
-  return 128 * qb_per_wave;
+int attn_block_rows(int prec, int qb) {
+  return prec == 1 ? 128 * qb : 128;
 }
 
 hipError_t launch_attn_bf16(const AttnParams& p, int H, int qb, bool out_f32, hipStream_t s) {

@@ -42,7 +42,7 @@ struct AttnParams {
 hipError_t launch_attn_bf16(const AttnParams& p, int H, int qb_per_wave, bool out_f32, hipStream_t s);
 hipError_t launch_attn_f32(const AttnParams& p, int H, hipStream_t s);
 hipError_t launch_attn_fp8(const AttnParams& p, int H, hipStream_t s);
-int attn_block_rows(int prec, int qb_per_wave);  // query rows per work item
+int attn_block_rows(int prec, int qb);  // query rows per work item (qb: BF16 query blocks per wave)
 
 // Transposed, zero-padded copy of V: v [tokens, H, D] (bf16 or u8 codes) ->
 // vt [H, D, padded tokens].

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -35,6 +36,7 @@ struct vggtx_ctx {
   int device;
   vggtx_config cfg;
   KernelTimer timer;
+  int attn_qb;  // BF16 attention: 32-row query blocks per wave (1 or 2)
 };
 
 namespace {
@@ -407,10 +409,11 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
                                           tn.second, H, st));
     }
     p.vt = io.vt;
-    for (auto& tn : make_tables(s, attn_block_rows(1, 1))) {
+    const int qb = ctx->attn_qb;
+    for (auto& tn : make_tables(s, attn_block_rows(1, qb))) {
       p.seqs = tn.first; p.n_items = tn.second;
       Span sp(ctx, cls, table_flops(tn.first, H), st);
-      VGGTX_HIP(launch_attn_bf16(p, H, 1, false, st));
+      VGGTX_HIP(launch_attn_bf16(p, H, qb, false, st));
     }
     return VGGTX_OK;
   }
@@ -664,6 +667,8 @@ vggtx_status vggtx_create(vggtx_handle* h, int device, const vggtx_config* cfg) 
   if (!c) return fail(VGGTX_E_INVALID, "out of host memory");
   c->device = device;
   c->cfg = *cfg;
+  c->attn_qb = 1;
+  if (const char* e = getenv("VGGTX_ATTN_QB")) c->attn_qb = (atoi(e) == 2) ? 2 : 1;
   *h = c;
   return VGGTX_OK;
 }
@@ -799,6 +804,25 @@ vggtx_status vggtx_timing_enable(vggtx_handle h, int enable) {
   t.cls.clear();
   t.flops.clear();
   t.dropped = 0;
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_timing_poll(vggtx_handle h, int64_t* finished, int64_t* recorded, int64_t* finished_attn_global) {
+  if (!h || !finished || !recorded) return fail(VGGTX_E_INVALID, "handle / output is null");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+  KernelTimer& t = h->timer;
+  int64_t done = 0, ga = 0;
+  for (size_t i = 0; i < t.cls.size(); ++i) {
+    const hipError_t e = hipEventQuery(t.ev[2 * i + 1]);
+    if (e == hipErrorNotReady) break;
+    if (e != hipSuccess) return fail(VGGTX_E_HIP, "hipEventQuery: %s", hipGetErrorString(e));
+    ++done;
+    if (t.cls[i] == VGGTX_K_ATTN_GLOBAL) ++ga;
+  }
+  *finished = done;
+  *recorded = (int64_t)t.cls.size();
+  if (finished_attn_global) *finished_attn_global = ga;
   return VGGTX_OK;
 }
 

@@ -16,7 +16,7 @@ __all__ = [
     "F32", "BF16", "FP8_E4M3", "OUT_F32", "OUT_BF16", "VggtxError", "library_path", "load",
     "Config", "BlockW", "PairW", "Layout", "Handle", "create", "destroy", "workspace_size",
     "aggregate", "aggregate_varlen", "block", "attn_workspace_size", "attn_frame", "attn_global",
-    "quantize_fp8", "status_str", "last_error", "BLOCK_FIELDS", "timing_enable", "timing_read",
+    "quantize_fp8", "status_str", "last_error", "BLOCK_FIELDS", "timing_enable", "timing_read", "timing_poll",
     "K_ATTN_GLOBAL", "K_ATTN_FRAME", "K_GEMM", "K_OTHER",
 ]
 
@@ -86,6 +86,8 @@ def load():
         "vggtx_quantize_fp8": [vp, vp, Layout, P_i32, i32, i32, i32, vp, vp, vp],
         "vggtx_timing_enable": [vp, i32],
         "vggtx_timing_read": [vp, ctypes.POINTER(Timing), ctypes.POINTER(ctypes.c_int64)],
+        "vggtx_timing_poll": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                              ctypes.POINTER(ctypes.c_int64)],
         "vggtx_status_str": [i32],
         "vggtx_last_error": [],
     }
@@ -261,6 +263,13 @@ def timing_read(h) -> dict:
     out = {names[i]: {"ms": arr[i].total_ms, "launches": arr[i].launches, "flops": arr[i].flops} for i in range(4)}
     out["dropped"] = dropped.value
     return out
+
+
+def timing_poll(h):
+    """(finished launches, recorded launches, finished global-attention launches); non-blocking."""
+    f, r, g = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().vggtx_timing_poll(h, ctypes.byref(f), ctypes.byref(r), ctypes.byref(g)))
+    return f.value, r.value, g.value
 
 
 class Handle:

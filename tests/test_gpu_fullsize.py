@@ -1,0 +1,117 @@
+"""Parity at the full VGGT-L shapes (C=1024, 16 heads x 64, MLP 4096, P=1374).
+
+* 24-layer aggregator at S=32 frames (43,968 global tokens), BF16: every
+  requested layer's global half is checked on 256 sampled rows against the
+  FP64 global block fed with the GPU's own frame-block output of that layer
+  (teacher forcing); the frame half on 4 frames against the FP64 frame block
+  fed with the previous layer's global output.  This measures each layer's
+  local error; the whole-network drift is covered at small sizes.
+* Global attention at S=1000 frames (1,374,000 tokens) in BF16 and FP8, and
+  over the 12-scene varlen batch, in the launch configuration the benchmark
+  times; the oracle evaluates sampled query rows against all keys.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import DEV, max_abs_rel, to_dev
+
+vg = pytest.importorskip("paper_2509_25191_amd.vggtx")
+pytestmark = pytest.mark.gpu
+
+P = 1374
+
+
+def _bf16_weights_dev(layers):
+    return [{part: {k: torch.from_numpy(v).to(DEV).to(torch.bfloat16) for k, v in blk.items()}
+             for part, blk in l.items()} for l in layers]
+
+
+def test_aggregate_vggt_l_s32_teacher_forced():
+    m = synth.ModelConfig()
+    S = 32
+    N = S * P
+    tokens, layers = synth.gen_problem(m, S, P, seed=0, bf16=True)
+    keep = [4, 11, 17, 23]
+    req = sorted(set(keep) | {l - 1 for l in keep})
+    h = vg.Handle(0, dim=m.dim, heads=m.heads, mlp_hidden=m.mlp_hidden)
+    out = vg.aggregate(h.h, to_dev(tokens, torch.float32), _bf16_weights_dev(layers), req, vg.BF16,
+                       out_dtype=vg.OUT_F32)
+    torch.cuda.synchronize()
+    C = m.dim
+    rows = synth.sample_rows(0, N, 256, P)
+    frames = [0, S - 1, 7, 19]
+    for l in keep:
+        i, ip = req.index(l), req.index(l - 1)
+        fo = out[i, :, :, :C].reshape(N, C).cpu().numpy().astype(np.float64)
+        go_rows = out[i, :, :, C:].reshape(N, C)[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+        ref_g = oracle.global_block_rows(fo, layers[l]["global"], rows, m.heads, m.ln_eps)
+        eg = max_abs_rel(go_rows, ref_g)
+        prev = out[ip, :, :, C:].reshape(N, C).cpu().numpy().astype(np.float64)
+        ref_f = oracle.frame_block_frames(prev, layers[l]["frame"], frames, P, m.heads, m.ln_eps)
+        got_f = out[i, frames, :, :C].cpu().numpy()
+        ef = max_abs_rel(got_f, ref_f)
+        print(f"S=32 layer {l}: frame half {ef:.3e}  global half {eg:.3e}")
+        assert ef < 2e-2 and eg < 2e-2
+    h.close()
+
+
+def _dev_qkv(N, H, seed, std_qk=0.64):
+    g = torch.Generator(device=DEV)
+    g.manual_seed(seed)
+    q = torch.empty((N, H, 64), device=DEV).normal_(0, std_qk, generator=g).to(torch.bfloat16)
+    k = torch.empty((N, H, 64), device=DEV).normal_(0, std_qk, generator=g).to(torch.bfloat16)
+    v = torch.empty((N, H, 64), device=DEV).normal_(0, 1.0, generator=g).to(torch.bfloat16)
+    return q, k, v
+
+
+def _check_rows(q, k, v, o, seq_start, seq_end, rows, heads):
+    """Oracle attention of the given rows (absolute indices inside [seq_start, seq_end))."""
+    errs = []
+    for hh in heads:
+        kk = k[seq_start:seq_end, hh].float().cpu().numpy()[None]
+        vv = v[seq_start:seq_end, hh].float().cpu().numpy()[None]
+        qq = q[rows, hh].float().cpu().numpy()[None]
+        ref = oracle.attention(qq, kk, vv)[0]
+        got = o[rows, hh].float().cpu().numpy()
+        errs.append(max_abs_rel(got, ref))
+    return max(errs)
+
+
+@pytest.mark.parametrize("prec,tol", [(vg.BF16, 2e-2), (vg.FP8_E4M3, 6e-2)])
+def test_attn_global_s1000_sampled_rows(prec, tol):
+    S, H = 1000, 16
+    N = S * P
+    h = vg.Handle(0, dim=1024, heads=16, mlp_hidden=4096)
+    q, k, v = _dev_qkv(N, H, seed=1000 + prec)
+    o = torch.empty_like(q)
+    vg.attn_global(h.h, q, k, v, o, [0, N], prec)
+    torch.cuda.synchronize()
+    rows = torch.from_numpy(synth.sample_rows(1000, N, 64, P)).to(DEV)
+    e = _check_rows(q, k, v, o, 0, N, rows, heads=[0, 7, 15])
+    print(f"S=1000 global attention prec={prec}: max_abs_rel on 64 rows x 3 heads = {e:.3e}")
+    assert e < tol
+    h.close()
+
+
+def test_attn_global_varlen_12_scenes_sampled_rows():
+    H = 16
+    frames = synth.varlen_scene_frames()
+    offs = np.concatenate([[0], np.cumsum(frames)]) * P
+    N = int(offs[-1])
+    h = vg.Handle(0, dim=1024, heads=16, mlp_hidden=4096)
+    q, k, v = _dev_qkv(N, H, seed=12)
+    o = torch.empty_like(q)
+    vg.attn_global(h.h, q, k, v, o, offs.tolist(), vg.BF16)
+    torch.cuda.synchronize()
+    worst = 0.0
+    rng = np.random.default_rng(12)
+    for i in range(len(frames)):
+        a, b = int(offs[i]), int(offs[i + 1])
+        rows = np.unique(np.concatenate([[a, b - 1], rng.integers(a, b, 6)]))
+        worst = max(worst, _check_rows(q, k, v, o, a, b, torch.from_numpy(rows).to(DEV), heads=[int(rng.integers(0, H))]))
+    print(f"varlen 12 scenes ({frames}) max_abs_rel = {worst:.3e}")
+    assert worst < 2e-2
+    h.close()
