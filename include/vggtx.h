@@ -179,6 +179,23 @@ vggtx_status vggtx_quantize_fp8(vggtx_handle h, const void* x, vggtx_layout in_l
                                 const int32_t* seq_offsets, int n_seq, int H, int D,
                                 uint8_t* codes, float* scales, void* stream);
 
+/* Attention autotuner.  Times every compiled tile variant of the attention
+ * kernel for `prec` (VGGTX_BF16: 1 or 2 query blocks of 32 rows per wave;
+ * VGGTX_FP8_E4M3: (query blocks per wave, waves per workgroup) in
+ * {(1,4), (2,4), (1,8), (2,8)}) on synthetic Q, K, V written into the
+ * caller's workspace (one sequence of `n_tokens` tokens, 16 heads of 64; a
+ * truncated problem of 8192 to 65536 tokens is representative since the kernels
+ * are compute bound) and keeps the fastest in the handle for all later calls.
+ * The workspace must hold vggtx_autotune_workspace_size() bytes; the call
+ * synchronises `stream`.  *chosen receives the variant index.  If the
+ * environment variable VGGTX_AUTOTUNE_CACHE names a file, a previously stored
+ * choice for (device architecture, prec) is reused without timing, and a new
+ * choice is appended to it.  Results never depend on the variant: every
+ * variant computes each query row with the same arithmetic in the same order. */
+vggtx_status vggtx_autotune_workspace_size(vggtx_handle h, int n_tokens, size_t* bytes);
+vggtx_status vggtx_autotune(vggtx_handle h, vggtx_prec prec, int n_tokens, void* ws, size_t ws_bytes, void* stream,
+                            int* chosen);
+
 /* Kernel timing (tracing).  While enabled, every kernel launch of the classes
  * below is bracketed by a pair of HIP events recorded on its launch stream, and
  * vggtx_timing_read() waits for those events and returns, per class, the summed

@@ -13,6 +13,8 @@
 // accumulator.  That makes the softmax statistics lane-local (plus one
 // exchange with lane l^32) and lets the probabilities feed the P V product
 // (O^T = V^T P^T) straight from registers.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -380,8 +382,9 @@ __device__ __forceinline__ uint32_t cvt_e4m3x2_inrange(float a, float b) {
 //      group g finds its 16 k-slots in one granule (slot j of group g <->
 //      key 32*(j/16) + 8*((j%16)/4) + 4*g + j%4), granules swizzled with
 //      (d >> 1) & 3.
-__global__ __launch_bounds__(256, 2) void attn_fp8_kernel(AttnParams p) {
-  constexpr int BN = 64, D = kHeadDim, BM = 128;
+template <int QB, int NW>
+__global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
+  constexpr int BN = 64, D = kHeadDim, BM = 32 * QB * NW, NT = 64 * NW;
   __shared__ __attribute__((aligned(16))) uint8_t Ks[2][BN * D];
   __shared__ __attribute__((aligned(16))) uint8_t Vs[2][D * BN];
 
@@ -397,31 +400,62 @@ __global__ __launch_bounds__(256, 2) void attn_fp8_kernel(AttnParams p) {
   const float* SV = p.sv + head * p.sc_hs + it.bb;
   const float vmax = p.vmax[head];
 
-  const int qrow = it.q0 + wave * 32 + r32;
   const i32x8 zero8 = {};
   const int one4 = 0x38383838;  // four E4M3 1.0 codes
   const i32x8 ones8 = {one4, one4, one4, one4, one4, one4, one4, one4};
-  const i32x8 qf = qrow < it.s1 ? *(const i32x8*)(Q + qrow * p.q_ts + 32 * g) : zero8;
-  const float sq = SQ[(it.q0 - it.s0) / kQuantRows];
+  i32x8 qf[QB];
+  float sq[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const int row = it.q0 + (wave * QB + qb) * 32 + r32;
+    qf[qb] = row < it.s1 ? *(const i32x8*)(Q + row * p.q_ts + 32 * g) : zero8;
+    // the 32 rows of a query block lie inside one 128-row scale block
+    sq[qb] = SQ[(it.q0 - it.s0 + (wave * QB + qb) * 32) / kQuantRows];
+  }
 
-  i32x4 kreg, vreg;
-  const int lr = tid >> 2, lch = tid & 3;
+  // K tile: 64 keys x 64 B; V tile: 64 d x 64 B; 512 granules of 16 B
+  constexpr int LPT = 512 / NT;  // granules per thread
+  i32x4 reg[LPT];
   auto gload = [&](int kt) {
     const i32x4 z = {};
-    const int key = kt + lr;
-    kreg = key < it.s1 ? *(const i32x4*)(K + key * p.k_ts + lch * 16) : z;
-    vreg = *(const i32x4*)(Vt + lr * p.vt_ds + (kt - it.s0) + lch * 16);
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int gi = tid + NT * i;
+      const int isv = gi >> 8, r = (gi >> 2) & 63, ch = gi & 3;
+      if (!isv) {
+        const int key = kt + r;
+        reg[i] = key < it.s1 ? *(const i32x4*)(K + key * p.k_ts + ch * 16) : z;
+      } else {
+        reg[i] = *(const i32x4*)(Vt + r * p.vt_ds + (kt - it.s0) + ch * 16);
+      }
+    }
   };
   auto lstore = [&](int buf) {
-    *(i32x4*)&Ks[buf][lr * D + ((lch ^ ((lr >> 1) & 3)) * 16)] = kreg;
-    const int kb = lch >> 1, h = lch & 1, sw = (lr >> 1) & 3;
-    const i32x2 a = {vreg[0], vreg[2]}, b = {vreg[1], vreg[3]};
-    *(i32x2*)&Vs[buf][lr * BN + (((2 * kb) ^ sw) * 16) + 8 * h] = a;
-    *(i32x2*)&Vs[buf][lr * BN + (((2 * kb + 1) ^ sw) * 16) + 8 * h] = b;
+#pragma unroll
+    for (int i = 0; i < LPT; ++i) {
+      const int gi = tid + NT * i;
+      const int isv = gi >> 8, r = (gi >> 2) & 63, ch = gi & 3;
+      const int sw = (r >> 1) & 3;
+      if (!isv) {
+        *(i32x4*)&Ks[buf][r * D + ((ch ^ sw) * 16)] = reg[i];
+      } else {
+        const int kb = ch >> 1, h = ch & 1;
+        const i32x2 a = {reg[i][0], reg[i][2]}, b = {reg[i][1], reg[i][3]};
+        *(i32x2*)&Vs[buf][r * BN + (((2 * kb) ^ sw) * 16) + 8 * h] = a;
+        *(i32x2*)&Vs[buf][r * BN + (((2 * kb + 1) ^ sw) * 16) + 8 * h] = b;
+      }
+    }
   };
 
-  f32x16 oacc[2] = {f32x16{}, f32x16{}};
-  float m_run = -INFINITY, l_run = 0.f;
+  f32x16 oacc[QB][2];
+  float m_run[QB], l_run[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    oacc[qb][0] = f32x16{};
+    oacc[qb][1] = f32x16{};
+    m_run[qb] = -INFINITY;
+    l_run[qb] = 0.f;
+  }
   const float c2 = p.scale_log2;
   const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
   gload(it.s0);
@@ -430,7 +464,7 @@ __global__ __launch_bounds__(256, 2) void attn_fp8_kernel(AttnParams p) {
   for (int t = 0; t < ntiles; ++t) {
     const int kt = it.s0 + t * BN, buf = t & 1;
     if (t + 1 < ntiles) gload(kt + BN);
-    i32x8 kf[2], vf[2];
+    i32x8 kf[2];
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
       const int r = kb * 32 + r32, sw = (r >> 1) & 3;
@@ -438,6 +472,61 @@ __global__ __launch_bounds__(256, 2) void attn_fp8_kernel(AttnParams p) {
       const i32x4 hi = *(const i32x4*)&Ks[buf][r * D + (((2 * g + 1) ^ sw) * 16)];
       kf[kb] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     }
+    f32x16 s[QB][2];
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      s[qb][0] = mfma_fp8(kf[0], qf[qb], f32x16{});
+      s[qb][1] = mfma_fp8(kf[1], qf[qb], f32x16{});
+    }
+    const int blk = (kt - it.s0) / kQuantRows;
+    const float sk = SK[blk];
+    const float rb = 448.f * SV[blk] / vmax;
+    const float lrb = __builtin_amdgcn_logf(rb);
+    const float inv_rb = 1.f / rb;
+    i32x8 pw[QB];
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      const float sigma = sq[qb] * sk * c2;
+      if (kt + BN > it.s1) {
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) s[qb][kb][i] = -INFINITY;
+      }
+      float m4[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const f32x16& sv = s[qb][j >> 1];
+        const int o = (j & 1) * 8;
+        m4[j] = __builtin_fmaxf(__builtin_fmaxf(__builtin_fmaxf(sv[o], sv[o + 1]), __builtin_fmaxf(sv[o + 2], sv[o + 3])),
+                                __builtin_fmaxf(__builtin_fmaxf(sv[o + 4], sv[o + 5]), __builtin_fmaxf(sv[o + 6], sv[o + 7])));
+      }
+      const float mx = lane_swap_max(__builtin_fmaxf(__builtin_fmaxf(m4[0], m4[1]), __builtin_fmaxf(m4[2], m4[3])));
+      const float m_new = __builtin_fmaxf(m_run[qb], mx * sigma);
+      if (__any(m_new > m_run[qb])) {
+        const float alpha = fast_exp2(m_run[qb] - m_new);
+        l_run[qb] *= alpha;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          oacc[qb][0][i] *= alpha;
+          oacc[qb][1][i] *= alpha;
+        }
+        m_run[qb] = m_new;
+      }
+      const float off = m_new - lrb;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int i = 0; i < 16; i += 4) {
+          const float e0 = fast_exp2(__builtin_fmaf(s[qb][kb][i], sigma, -off));
+          const float e1 = fast_exp2(__builtin_fmaf(s[qb][kb][i + 1], sigma, -off));
+          const float e2 = fast_exp2(__builtin_fmaf(s[qb][kb][i + 2], sigma, -off));
+          const float e3 = fast_exp2(__builtin_fmaf(s[qb][kb][i + 3], sigma, -off));
+          pw[qb][(16 * kb + i) >> 2] = (int)(cvt_e4m3x2_inrange(e0, e1) | (cvt_e4m3x2_inrange(e2, e3) << 16));
+        }
+    }
+    i32x8 vf[2];
 #pragma unroll
     for (int db = 0; db < 2; ++db) {
       const int d = db * 32 + r32, sw = (d >> 1) & 3;
@@ -445,70 +534,32 @@ __global__ __launch_bounds__(256, 2) void attn_fp8_kernel(AttnParams p) {
       const i32x4 hi = *(const i32x4*)&Vs[buf][d * BN + (((2 + g) ^ sw) * 16)];
       vf[db] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     }
-    f32x16 s[2];
-    s[0] = mfma_fp8(kf[0], qf, f32x16{});
-    s[1] = mfma_fp8(kf[1], qf, f32x16{});
-    const int blk = (kt - it.s0) / kQuantRows;
-    const float sigma = sq * SK[blk] * c2;
-    const float rb = 448.f * SV[blk] / vmax;
-    if (kt + BN > it.s1) {
 #pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-          if (kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) s[kb][i] = -INFINITY;
+    for (int qb = 0; qb < QB; ++qb) {
+      const f32x16 lsum = mfma_fp8(ones8, pw[qb], f32x16{});
+      oacc[qb][0] = mfma_fp8(vf[0], pw[qb], oacc[qb][0]);
+      oacc[qb][1] = mfma_fp8(vf[1], pw[qb], oacc[qb][1]);
+      l_run[qb] = __builtin_fmaf(lsum[0], inv_rb, l_run[qb]);
     }
-    float m4[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const f32x16& sv = s[j >> 1];
-      const int o = (j & 1) * 8;
-      m4[j] = __builtin_fmaxf(__builtin_fmaxf(__builtin_fmaxf(sv[o], sv[o + 1]), __builtin_fmaxf(sv[o + 2], sv[o + 3])),
-                              __builtin_fmaxf(__builtin_fmaxf(sv[o + 4], sv[o + 5]), __builtin_fmaxf(sv[o + 6], sv[o + 7])));
-    }
-    const float mx = lane_swap_max(__builtin_fmaxf(__builtin_fmaxf(m4[0], m4[1]), __builtin_fmaxf(m4[2], m4[3])));
-    const float m_new = __builtin_fmaxf(m_run, mx * sigma);
-    if (__any(m_new > m_run)) {
-      const float alpha = fast_exp2(m_run - m_new);
-      l_run *= alpha;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        oacc[0][i] *= alpha;
-        oacc[1][i] *= alpha;
-      }
-      m_run = m_new;
-    }
-    const float off = m_new - __builtin_amdgcn_logf(rb);
-    i32x8 pw;
-#pragma unroll
-    for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-      for (int i = 0; i < 16; i += 4) {
-        const float e0 = fast_exp2(__builtin_fmaf(s[kb][i], sigma, -off));
-        const float e1 = fast_exp2(__builtin_fmaf(s[kb][i + 1], sigma, -off));
-        const float e2 = fast_exp2(__builtin_fmaf(s[kb][i + 2], sigma, -off));
-        const float e3 = fast_exp2(__builtin_fmaf(s[kb][i + 3], sigma, -off));
-        pw[(16 * kb + i) >> 2] = (int)(cvt_e4m3x2_inrange(e0, e1) | (cvt_e4m3x2_inrange(e2, e3) << 16));
-      }
-    const f32x16 lsum = mfma_fp8(ones8, pw, f32x16{});
-    l_run = __builtin_fmaf(lsum[0], 1.f / rb, l_run);
-    oacc[0] = mfma_fp8(vf[0], pw, oacc[0]);
-    oacc[1] = mfma_fp8(vf[1], pw, oacc[1]);
     if (t + 1 < ntiles) lstore(buf ^ 1);
     __syncthreads();
   }
-  const float inv = vmax / 448.f / l_run;
-  if (qrow < it.s1) {
 #pragma unroll
-    for (int db = 0; db < 2; ++db)
+  for (int qb = 0; qb < QB; ++qb) {
+    const float inv = vmax / 448.f / l_run[qb];
+    const int qrow = it.q0 + (wave * QB + qb) * 32 + r32;
+    if (qrow < it.s1) {
 #pragma unroll
-      for (int i = 0; i < 16; i += 4) {
-        const int d = db * 32 + 8 * (i >> 2) + 4 * g;
-        bf16* o = (bf16*)p.o + qrow * p.o_ts + head * p.o_hs + d;
-        const bf16x4 v = {f2bf(oacc[db][i] * inv), f2bf(oacc[db][i + 1] * inv), f2bf(oacc[db][i + 2] * inv),
-                          f2bf(oacc[db][i + 3] * inv)};
-        *(bf16x4*)o = v;
-      }
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int i = 0; i < 16; i += 4) {
+          const int d = db * 32 + 8 * (i >> 2) + 4 * g;
+          bf16* o = (bf16*)p.o + qrow * p.o_ts + head * p.o_hs + d;
+          const bf16x4 v = {f2bf(oacc[qb][db][i] * inv), f2bf(oacc[qb][db][i + 1] * inv),
+                            f2bf(oacc[qb][db][i + 2] * inv), f2bf(oacc[qb][db][i + 3] * inv)};
+          *(bf16x4*)o = v;
+        }
+    }
   }
 }
 
@@ -628,8 +679,13 @@ __global__ void scale_max_kernel(const float* scales, int64_t sc_hs, int n_block
 }
 
 // ============================================================== launchers
-int attn_block_rows(int prec, int qb) {
-  return prec == 1 ? 128 * qb : 128;
+int attn_block_rows(int prec, int variant) {
+  if (prec == 1) return 128 * variant;                // BF16: query blocks per wave (1 or 2), 4 waves
+  if (prec == 2) {                                    // FP8 variants: (QB, waves) = (1,4) (2,4) (1,8) (2,8)
+    static const int rows[4] = {128, 256, 256, 512};
+    return rows[variant & 3];
+  }
+  return 128;
 }
 
 hipError_t launch_attn_bf16(const AttnParams& p, int H, int qb, bool out_f32, hipStream_t s) {
@@ -649,8 +705,14 @@ hipError_t launch_attn_f32(const AttnParams& p, int H, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_attn_fp8(const AttnParams& p, int H, hipStream_t s) {
-  hipLaunchKernelGGL(attn_fp8_kernel, dim3(p.n_items, H), dim3(256), 0, s, p);
+hipError_t launch_attn_fp8(const AttnParams& p, int H, int variant, hipStream_t s) {
+  const dim3 grid(p.n_items, H);
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((attn_fp8_kernel<2, 4>), grid, dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL((attn_fp8_kernel<1, 8>), grid, dim3(512), 0, s, p); break;
+    case 3: hipLaunchKernelGGL((attn_fp8_kernel<2, 8>), grid, dim3(512), 0, s, p); break;
+    default: hipLaunchKernelGGL((attn_fp8_kernel<1, 4>), grid, dim3(256), 0, s, p); break;
+  }
   return hipGetLastError();
 }
 

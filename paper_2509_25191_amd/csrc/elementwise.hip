@@ -1,6 +1,8 @@
 // LayerNorm of the float32 residual stream (the pre-LN of both sub-blocks).
 // One wave per row; mean and biased variance in float32 (two passes over the
 // row held in registers), output in the GEMM operand type.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -64,6 +66,27 @@ hipError_t launch_layernorm(const float* x, int64_t ldx, const void* g, const vo
   if (rows <= 0) return hipSuccess;
   return bf16_io ? ln_dispatch<bf16>(x, ldx, g, b, eps, h, ldh, rows, C, s)
                  : ln_dispatch<float>(x, ldx, g, b, eps, h, ldh, rows, C, s);
+}
+
+// Seeded synthetic bfloat16 values for the autotuner: a counter-based hash
+// (SplitMix64 finaliser) of (seed, index) mapped to a uniform value in
+// [-scale, scale).
+__global__ void fill_hash_bf16_kernel(bf16* x, int64_t n, uint64_t seed, float scale) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    const float u = (float)(z >> 40) * (1.f / 16777216.f);  // [0, 1)
+    x[i] = f2bf((2.f * u - 1.f) * scale);
+  }
+}
+
+hipError_t launch_fill_hash_bf16(bf16* x, int64_t n, uint64_t seed, float scale, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_hash_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, seed, scale);
+  return hipGetLastError();
 }
 
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s) {

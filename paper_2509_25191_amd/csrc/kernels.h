@@ -41,8 +41,9 @@ struct AttnParams {
 // ---- attention (attention.hip)
 hipError_t launch_attn_bf16(const AttnParams& p, int H, int qb_per_wave, bool out_f32, hipStream_t s);
 hipError_t launch_attn_f32(const AttnParams& p, int H, hipStream_t s);
-hipError_t launch_attn_fp8(const AttnParams& p, int H, hipStream_t s);
-int attn_block_rows(int prec, int qb);  // query rows per work item (qb: BF16 query blocks per wave)
+// FP8 variants: 0 = (1 query block per wave, 4 waves), 1 = (2, 4), 2 = (1, 8), 3 = (2, 8)
+hipError_t launch_attn_fp8(const AttnParams& p, int H, int variant, hipStream_t s);
+int attn_block_rows(int prec, int variant);  // query rows per work item of a kernel variant
 
 // Transposed, zero-padded copy of V: v [tokens, H, D] (bf16 or u8 codes) ->
 // vt [H, D, padded tokens].
@@ -83,5 +84,6 @@ hipError_t launch_gemm_f32(const GemmParams& p, Epi epi, hipStream_t s);
 hipError_t launch_layernorm(const float* x, int64_t ldx, const void* g, const void* b, float eps, void* h,
                             int64_t ldh, int rows, int C, bool bf16_io, hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_fill_hash_bf16(bf16* x, int64_t n, uint64_t seed, float scale, hipStream_t s);
 
 }  // namespace vggtx

@@ -12,6 +12,8 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <fstream>
+#include <sstream>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -34,9 +36,11 @@ struct KernelTimer {
 
 struct vggtx_ctx {
   int device;
+  char arch[64];
   vggtx_config cfg;
   KernelTimer timer;
-  int attn_qb;  // BF16 attention: 32-row query blocks per wave (1 or 2)
+  int attn_qb;      // BF16 attention: 32-row query blocks per wave (1 or 2)
+  int fp8_variant;  // FP8 attention tile variant (see launch_attn_fp8)
 };
 
 namespace {
@@ -409,7 +413,8 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
                                           tn.second, H, st));
     }
     p.vt = io.vt;
-    const int qb = ctx->attn_qb;
+    // frames (P of order 10^3 tokens) keep 128-row work items to limit tail waste
+    const int qb = cls == VGGTX_K_ATTN_FRAME ? 1 : ctx->attn_qb;
     for (auto& tn : make_tables(s, attn_block_rows(1, qb))) {
       p.seqs = tn.first; p.n_items = tn.second;
       Span sp(ctx, cls, table_flops(tn.first, H), st);
@@ -434,10 +439,11 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
   p.k = io.k8; p.k_ts = kHeadDim; p.k_hs = N * kHeadDim;
   p.vt = io.v8t;
   p.sq = io.sq; p.sk = io.sk; p.sv = io.sv; p.sc_hs = io.nblk; p.vmax = io.vmax;
-  for (auto& tn : make_tables(s, attn_block_rows(2, 1))) {
+  const int fv = ctx->fp8_variant;
+  for (auto& tn : make_tables(s, attn_block_rows(2, fv))) {
     p.seqs = tn.first; p.n_items = tn.second;
     Span sp(ctx, cls, table_flops(tn.first, H), st);
-    VGGTX_HIP(launch_attn_fp8(p, H, st));
+    VGGTX_HIP(launch_attn_fp8(p, H, fv, st));
   }
   return VGGTX_OK;
 }
@@ -666,9 +672,13 @@ vggtx_status vggtx_create(vggtx_handle* h, int device, const vggtx_config* cfg) 
   vggtx_ctx* c = new (std::nothrow) vggtx_ctx;
   if (!c) return fail(VGGTX_E_INVALID, "out of host memory");
   c->device = device;
+  snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
   c->cfg = *cfg;
-  c->attn_qb = 1;
+  // defaults measured on MI355X (VGGT-L shapes); vggtx_autotune can re-pick them
+  c->attn_qb = 2;
   if (const char* e = getenv("VGGTX_ATTN_QB")) c->attn_qb = (atoi(e) == 2) ? 2 : 1;
+  c->fp8_variant = 1;
+  if (const char* e = getenv("VGGTX_FP8_VARIANT")) c->fp8_variant = atoi(e) & 3;
   *h = c;
   return VGGTX_OK;
 }
@@ -788,6 +798,130 @@ vggtx_status vggtx_quantize_fp8(vggtx_handle h, const void* x, vggtx_layout in_l
   for (auto& tn : make_tables(s, kQuantRows))
     VGGTX_HIP(launch_quant_fp8((const bf16*)x, in_layout.token_stride, in_layout.head_stride, codes, N * kHeadDim, 0,
                                false, scales, nblk, tn.first, tn.second, H, (hipStream_t)stream));
+  return VGGTX_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+namespace {
+
+constexpr int kTuneHeads = 16;
+
+int n_variants(vggtx_prec prec) { return prec == VGGTX_FP8_E4M3 ? 4 : (prec == VGGTX_BF16 ? 2 : 1); }
+
+void set_variant(vggtx_ctx* c, vggtx_prec prec, int v) {
+  if (prec == VGGTX_BF16) c->attn_qb = v + 1;
+  if (prec == VGGTX_FP8_E4M3) c->fp8_variant = v;
+}
+
+bool cache_lookup(const char* path, const char* arch, int prec, int* variant) {
+  std::ifstream f(path);
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream ss(line);
+    std::string a;
+    int pr = -1, v = -1;
+    if (ss >> a >> pr >> v && a == arch && pr == prec && v >= 0 && v < n_variants((vggtx_prec)prec)) {
+      *variant = v;  // the last matching line wins
+      found = true;
+    }
+  }
+  return found;
+}
+
+}  // namespace
+
+vggtx_status vggtx_autotune_workspace_size(vggtx_handle h, int n_tokens, size_t* bytes) {
+  if (!h || !bytes) return fail(VGGTX_E_INVALID, "handle / bytes is null");
+  if (n_tokens <= 0) return fail(VGGTX_E_INVALID, "n_tokens = %d", n_tokens);
+  const int64_t N = n_tokens, C = (int64_t)kTuneHeads * kHeadDim;
+  const Seqs s = [&] { Seqs q; q.uniform = true; q.first = 0; q.len = n_tokens; q.n = 1; return q; }();
+  const size_t qkvo = (size_t)round_up(N * C * 2, 256) * 4;
+  *bytes = qkvo + carve_attn(kTuneHeads, N, s.padded_cols(), s.scale_blocks(), VGGTX_FP8_E4M3, nullptr).total +
+           carve_attn(kTuneHeads, N, s.padded_cols(), s.scale_blocks(), VGGTX_BF16, nullptr).total;
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_autotune(vggtx_handle h, vggtx_prec prec, int n_tokens, void* ws, size_t ws_bytes, void* stream,
+                            int* chosen) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  VGGTX_TRY(check_prec(prec));
+  if (n_tokens < 256 || n_tokens > (1 << 20)) return fail(VGGTX_E_INVALID, "n_tokens %d outside [256, 2^20]", n_tokens);
+  size_t need = 0;
+  VGGTX_TRY(vggtx_autotune_workspace_size(h, n_tokens, &need));
+  if (!ws || ws_bytes < need) return fail(VGGTX_E_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need);
+  if ((uintptr_t)ws % 256) return fail(VGGTX_E_INVALID, "workspace must be 256-byte aligned");
+  const int nv = n_variants(prec);
+  const char* cache = getenv("VGGTX_AUTOTUNE_CACHE");
+  int v_cached = -1;
+  if (cache && cache_lookup(cache, h->arch, (int)prec, &v_cached)) {
+    set_variant(h, prec, v_cached);
+    if (chosen) *chosen = v_cached;
+    return VGGTX_OK;
+  }
+  if (nv == 1) {
+    if (chosen) *chosen = 0;
+    return VGGTX_OK;
+  }
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t N = n_tokens, C = (int64_t)kTuneHeads * kHeadDim;
+  const size_t slab = (size_t)round_up(N * C * 2, 256);
+  char* base = (char*)ws;
+  bf16* q = (bf16*)base;
+  bf16* k = (bf16*)(base + slab);
+  bf16* v = (bf16*)(base + 2 * slab);
+  bf16* o = (bf16*)(base + 3 * slab);
+  void* aws = base + 4 * slab;
+  const size_t aws_bytes = ws_bytes - 4 * slab;
+  // synthetic operands with the random-init logit spread (q, k std ~0.64)
+  VGGTX_HIP(launch_fill_hash_bf16(q, N * C, 1, 1.1f, st));
+  VGGTX_HIP(launch_fill_hash_bf16(k, N * C, 2, 1.1f, st));
+  VGGTX_HIP(launch_fill_hash_bf16(v, N * C, 3, 1.7f, st));
+  const vggtx_layout lay{C, kHeadDim};
+  const int32_t offs[2] = {0, n_tokens};
+  hipEvent_t e0, e1;
+  VGGTX_HIP(hipEventCreate(&e0));
+  VGGTX_HIP(hipEventCreate(&e1));
+  const int saved_qb = h->attn_qb, saved_fv = h->fp8_variant;
+  const bool saved_timer = h->timer.enabled;
+  h->timer.enabled = false;
+  int best = 0;
+  float best_ms = 1e30f;
+  vggtx_status rc = VGGTX_OK;
+  for (int var = 0; var < nv && rc == VGGTX_OK; ++var) {
+    set_variant(h, prec, var);
+    float ms_min = 1e30f;
+    for (int rep = 0; rep < 3 && rc == VGGTX_OK; ++rep) {  // first repetition warms up
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(VGGTX_E_HIP, "hipEventRecord"); break; }
+      rc = vggtx_attn_global(h, q, k, v, o, offs, 1, kTuneHeads, kHeadDim, lay, lay, prec, aws, aws_bytes, stream);
+      if (rc != VGGTX_OK) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        rc = fail(VGGTX_E_HIP, "timing events failed");
+        break;
+      }
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (rep > 0) ms_min = std::min(ms_min, ms);
+    }
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = var;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->timer.enabled = saved_timer;
+  h->attn_qb = saved_qb;
+  h->fp8_variant = saved_fv;
+  if (rc != VGGTX_OK) return rc;
+  set_variant(h, prec, best);
+  if (chosen) *chosen = best;
+  if (cache) {
+    std::ofstream f(cache, std::ios::app);
+    if (f) f << h->arch << " " << (int)prec << " " << best << " " << best_ms << "\n";
+  }
   return VGGTX_OK;
 }
 

@@ -17,6 +17,7 @@ __all__ = [
     "Config", "BlockW", "PairW", "Layout", "Handle", "create", "destroy", "workspace_size",
     "aggregate", "aggregate_varlen", "block", "attn_workspace_size", "attn_frame", "attn_global",
     "quantize_fp8", "status_str", "last_error", "BLOCK_FIELDS", "timing_enable", "timing_read", "timing_poll",
+    "autotune_workspace_size", "autotune",
     "K_ATTN_GLOBAL", "K_ATTN_FRAME", "K_GEMM", "K_OTHER",
 ]
 
@@ -84,6 +85,8 @@ def load():
         "vggtx_attn_frame": [vp, vp, vp, vp, vp, i32, i32, i32, i32, Layout, Layout, i32, vp, sz, vp],
         "vggtx_attn_global": [vp, vp, vp, vp, vp, P_i32, i32, i32, i32, Layout, Layout, i32, vp, sz, vp],
         "vggtx_quantize_fp8": [vp, vp, Layout, P_i32, i32, i32, i32, vp, vp, vp],
+        "vggtx_autotune_workspace_size": [vp, i32, ctypes.POINTER(sz)],
+        "vggtx_autotune": [vp, i32, i32, vp, sz, vp, ctypes.POINTER(i32)],
         "vggtx_timing_enable": [vp, i32],
         "vggtx_timing_read": [vp, ctypes.POINTER(Timing), ctypes.POINTER(ctypes.c_int64)],
         "vggtx_timing_poll": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -248,6 +251,23 @@ def quantize_fp8(h, x, seq_offsets: Sequence[int], codes=None, scales=None, stre
     _check(load().vggtx_quantize_fp8(h, _ptr(x), _layout(x), _i32_array(seq_offsets), len(seq_offsets) - 1, H, D,
                                      _ptr(codes), _ptr(scales), _stream(stream)))
     return codes, scales
+
+
+def autotune_workspace_size(h, n_tokens: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load().vggtx_autotune_workspace_size(h, int(n_tokens), ctypes.byref(n)))
+    return n.value
+
+
+def autotune(h, prec: int, n_tokens: int = 32768, ws: Optional[torch.Tensor] = None, stream=None,
+             device="cuda") -> int:
+    """Pick the fastest attention tile variant for `prec`; returns its index."""
+    if ws is None:
+        ws = _alloc_ws(autotune_workspace_size(h, n_tokens), device)
+    chosen = ctypes.c_int()
+    _check(load().vggtx_autotune(h, int(prec), int(n_tokens), _ptr(ws), ws.numel(), _stream(stream),
+                                 ctypes.byref(chosen)))
+    return chosen.value
 
 
 def timing_enable(h, enable: bool = True) -> None:

@@ -164,3 +164,60 @@ def test_quantize_fp8_bit_exact(handle):
             np.testing.assert_array_equal(codes[h, a:b], rc[a:b])
             np.testing.assert_array_equal(scales[h, blk:blk + len(starts)], rs)
         blk += len(starts)
+
+
+def _handle_with(env):
+    import os
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return vg.Handle(0, dim=1024, heads=16, mlp_hidden=4096)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("prec,key,values", [(vg.FP8_E4M3, "VGGTX_FP8_VARIANT", [0, 1, 2, 3]),
+                                             (vg.BF16, "VGGTX_ATTN_QB", [1, 2])])
+def test_tile_variants_are_bitwise_identical(prec, key, values):
+    """Every tile variant computes each query row with the same arithmetic in the same order."""
+    H, D = 16, 64
+    offs = [0, 700, 701, 1500, 3100]
+    q, k, v = _qkv(H, offs[-1], D, "R1", seed=8)
+    qd, kd, vd = (_dev_tokens(a, prec) for a in (q, k, v))
+    outs = []
+    for val in values:
+        h = _handle_with({key: val})
+        o = torch.zeros_like(qd)
+        vg.attn_global(h.h, qd, kd, vd, o, offs, prec)
+        torch.cuda.synchronize()
+        outs.append(o)
+        h.close()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+def test_autotune_picks_a_variant_and_caches_it(tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("VGGTX_AUTOTUNE_CACHE", str(cache))
+    h = vg.Handle(0, dim=1024, heads=16, mlp_hidden=4096)
+    v8 = vg.autotune(h.h, vg.FP8_E4M3, n_tokens=8192)
+    vb = vg.autotune(h.h, vg.BF16, n_tokens=8192)
+    assert 0 <= v8 < 4 and 0 <= vb < 2
+    lines = cache.read_text().split()
+    assert len(lines) == 8  # two records of (arch, prec, variant, ms)
+    # a second handle reuses the cached choice without timing
+    h2 = vg.Handle(0, dim=1024, heads=16, mlp_hidden=4096)
+    assert vg.autotune(h2.h, vg.FP8_E4M3, n_tokens=8192) == v8
+    # results after tuning still match the oracle
+    H, D, N = 16, 64, 900
+    q, k, v = _qkv(H, N, D, "R0", seed=9)
+    qd, kd, vd = (_dev_tokens(a, vg.FP8_E4M3) for a in (q, k, v))
+    o = torch.zeros_like(qd)
+    vg.attn_global(h.h, qd, kd, vd, o, [0, N], vg.FP8_E4M3)
+    torch.cuda.synchronize()
+    assert max_abs_rel(o.float().cpu().numpy().transpose(1, 0, 2), oracle.attention(q, k, v)) < 6e-2
+    h.close(); h2.close()
