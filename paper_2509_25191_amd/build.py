@@ -33,9 +33,15 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found: the vggtx library needs ROCm's hipcc to build")
 
 
+# Per-file additions.  The attention kernels never produce or consume NaN
+# (masked scores are -inf, never NaN), so max() needs no NaN quieting of the
+# MFMA results; infinities stay honoured.
+FILE_FLAGS = {"attention.hip": ["-fno-honor-nans"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")

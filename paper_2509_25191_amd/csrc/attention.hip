@@ -59,11 +59,11 @@ __device__ __forceinline__ float lane_swap_max(float v) {
 //
 // LDS tiles (BN = 64 keys, D = 64), 16-byte granules XOR-swizzled with the row
 // index to keep ds_read_b128 conflict free:
-//   Ks[key][d]      granule (d/8) ^ (key & 7)
+//   Ks[key][d]      granule (d/8) ^ lds_swz8(key)
 //   Vs[d][key']     transposed V; inside every 16-key group the keys are
 //                   stored in the order in which a lane's MFMA k-slots need
 //                   them (slot j of lane group g <-> key 8*(j/4) + 4*g + j%4),
-//                   granule ^ (d & 7).
+//                   granule ^ lds_swz8(d).
 template <int QB, bool OUT_F32>
 __global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
   constexpr int BN = 64, D = kHeadDim, BM = 128 * QB;
@@ -103,12 +103,12 @@ __global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int r = (tid >> 3) + 32 * i, ch = tid & 7;
-      *(bf16x8*)&Ks[buf][r * D + ((ch ^ (r & 7)) * 8)] = kreg[i];
+      *(bf16x8*)&Ks[buf][r * D + ((ch ^ lds_swz8(r)) * 8)] = kreg[i];
       const int hp = ch >> 1, a = ch & 1;
       const bf16x4 lo = {vreg[i][0], vreg[i][1], vreg[i][2], vreg[i][3]};
       const bf16x4 hi = {vreg[i][4], vreg[i][5], vreg[i][6], vreg[i][7]};
-      *(bf16x4*)&Vs[buf][r * BN + (((2 * hp) ^ (r & 7)) * 8) + 4 * a] = lo;
-      *(bf16x4*)&Vs[buf][r * BN + (((2 * hp + 1) ^ (r & 7)) * 8) + 4 * a] = hi;
+      *(bf16x4*)&Vs[buf][r * BN + (((2 * hp) ^ lds_swz8(r)) * 8) + 4 * a] = lo;
+      *(bf16x4*)&Vs[buf][r * BN + (((2 * hp + 1) ^ lds_swz8(r)) * 8) + 4 * a] = hi;
     }
   };
 
@@ -128,7 +128,10 @@ __global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
   lstore(0);
   __syncthreads();
 
-  for (int t = 0; t < ntiles; ++t) {
+  // One key tile; MASKED is set only for the final, partial tile of a
+  // sequence, so full tiles carry no key-bound checks.
+  auto tile = [&](int t, auto masked) {
+    constexpr bool MASKED = decltype(masked)::value;
     const int kt = it.s0 + t * BN, buf = t & 1;
     if (t + 1 < ntiles) gload(kt + BN);
 
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int r = kb * 32 + r32;
-          kf[kb][c] = *(const bf16x8*)&Ks[buf][r * D + (((2 * c + g) ^ (r & 7)) * 8)];
+          kf[kb][c] = *(const bf16x8*)&Ks[buf][r * D + (((2 * c + g) ^ lds_swz8(r)) * 8)];
         }
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb)
@@ -154,11 +157,10 @@ __global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
     }
 
     // Phase 2: online softmax; probabilities packed as bf16 PV operands.
-    const bool tail = kt + BN > it.s1;
     bf16x8 pb[QB][2][2];
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-      if (tail) {
+      if (MASKED) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const int d = db * 32 + r32;
-            vf[db][kb][h] = *(const bf16x8*)&Vs[buf][d * BN + (((2 * (2 * kb + h) + g) ^ (d & 7)) * 8)];
+            vf[db][kb][h] = *(const bf16x8*)&Vs[buf][d * BN + (((2 * (2 * kb + h) + g) ^ lds_swz8(d)) * 8)];
           }
 #pragma unroll
       for (int qb = 0; qb < QB; ++qb)
@@ -219,9 +221,15 @@ __global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
             for (int h = 0; h < 2; ++h) oacc[qb][db] = mfma_bf16(vf[db][kb][h], pb[qb][kb][h], oacc[qb][db]);
     }
 
-    if (t + 1 < ntiles) lstore(buf ^ 1);
-    __syncthreads();
-  }
+    if (t + 1 < ntiles) {
+      lstore(buf ^ 1);
+      __syncthreads();
+    }
+  };
+  const bool ragged = (it.s1 - it.s0) % BN != 0;
+  const int nfull = ntiles - (ragged ? 1 : 0);
+  for (int t = 0; t < nfull; ++t) tile(t, std::false_type{});
+  if (ragged) tile(ntiles - 1, std::true_type{});
 
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
@@ -360,8 +368,12 @@ __global__ __launch_bounds__(256, 1) void attn_f32_kernel(AttnParams p) {
 // E4M3 conversion of values known to lie in [0, 448 * (1 + 2^-20)]: the
 // folded probabilities below never exceed r_b <= 448 because the running
 // maximum is exact, so no clamp is needed before the hardware converter.
-__device__ __forceinline__ uint32_t cvt_e4m3x2_inrange(float a, float b) {
-  return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false) & 0xffffu;
+// Four in-range floats -> four E4M3 codes in one dword (bytes in argument
+// order).  The first conversion fills the low half (its high half is
+// scratch), the second writes the high half in place.
+__device__ __forceinline__ int pack_e4m3x4(float e0, float e1, float e2, float e3) {
+  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(e0, e1, __float_as_int(e0), false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(e2, e3, lo, true);
 }
 
 // Global attention on OCP E4M3 operands (MFMA 32x32x64 f8f6f4, one MFMA per
@@ -377,11 +389,11 @@ __device__ __forceinline__ uint32_t cvt_e4m3x2_inrange(float a, float b) {
 // product (one extra MFMA against an all-ones operand), so the output stays
 // a convex combination of value rows whatever the rounding of P.
 //
-// LDS: Ks[key][d] bytes, 16-byte granules swizzled with (key >> 1) & 3;
+// LDS: Ks[key][d] bytes, 16-byte granules swizzled with lds_swz4(key);
 //      Vs[d][key'] bytes, keys of every 32-key block permuted so that lane
 //      group g finds its 16 k-slots in one granule (slot j of group g <->
 //      key 32*(j/16) + 8*((j%16)/4) + 4*g + j%4), granules swizzled with
-//      (d >> 1) & 3.
+//      lds_swz4(d).
 template <int QB, int NW>
 __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
   constexpr int BN = 64, D = kHeadDim, BM = 32 * QB * NW, NT = 64 * NW;
@@ -435,7 +447,7 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
     for (int i = 0; i < LPT; ++i) {
       const int gi = tid + NT * i;
       const int isv = gi >> 8, r = (gi >> 2) & 63, ch = gi & 3;
-      const int sw = (r >> 1) & 3;
+      const int sw = lds_swz4(r);
       if (!isv) {
         *(i32x4*)&Ks[buf][r * D + ((ch ^ sw) * 16)] = reg[i];
       } else {
@@ -461,13 +473,16 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
   gload(it.s0);
   lstore(0);
   __syncthreads();
-  for (int t = 0; t < ntiles; ++t) {
+  // One key tile; MASKED is set only for the final, partial tile of a
+  // sequence, so full tiles carry no key-bound checks.
+  auto tile = [&](int t, auto masked) {
+    constexpr bool MASKED = decltype(masked)::value;
     const int kt = it.s0 + t * BN, buf = t & 1;
     if (t + 1 < ntiles) gload(kt + BN);
     i32x8 kf[2];
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
-      const int r = kb * 32 + r32, sw = (r >> 1) & 3;
+      const int r = kb * 32 + r32, sw = lds_swz4(r);
       const i32x4 lo = *(const i32x4*)&Ks[buf][r * D + (((2 * g) ^ sw) * 16)];
       const i32x4 hi = *(const i32x4*)&Ks[buf][r * D + (((2 * g + 1) ^ sw) * 16)];
       kf[kb] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
@@ -487,7 +502,7 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
       const float sigma = sq[qb] * sk * c2;
-      if (kt + BN > it.s1) {
+      if (MASKED) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
@@ -523,13 +538,13 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
           const float e1 = fast_exp2(__builtin_fmaf(s[qb][kb][i + 1], sigma, -off));
           const float e2 = fast_exp2(__builtin_fmaf(s[qb][kb][i + 2], sigma, -off));
           const float e3 = fast_exp2(__builtin_fmaf(s[qb][kb][i + 3], sigma, -off));
-          pw[qb][(16 * kb + i) >> 2] = (int)(cvt_e4m3x2_inrange(e0, e1) | (cvt_e4m3x2_inrange(e2, e3) << 16));
+          pw[qb][(16 * kb + i) >> 2] = pack_e4m3x4(e0, e1, e2, e3);
         }
     }
     i32x8 vf[2];
 #pragma unroll
     for (int db = 0; db < 2; ++db) {
-      const int d = db * 32 + r32, sw = (d >> 1) & 3;
+      const int d = db * 32 + r32, sw = lds_swz4(d);
       const i32x4 lo = *(const i32x4*)&Vs[buf][d * BN + ((g ^ sw) * 16)];
       const i32x4 hi = *(const i32x4*)&Vs[buf][d * BN + (((2 + g) ^ sw) * 16)];
       vf[db] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
@@ -541,9 +556,15 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
       oacc[qb][1] = mfma_fp8(vf[1], pw[qb], oacc[qb][1]);
       l_run[qb] = __builtin_fmaf(lsum[0], inv_rb, l_run[qb]);
     }
-    if (t + 1 < ntiles) lstore(buf ^ 1);
-    __syncthreads();
-  }
+    if (t + 1 < ntiles) {
+      lstore(buf ^ 1);
+      __syncthreads();
+    }
+  };
+  const bool ragged = (it.s1 - it.s0) % BN != 0;
+  const int nfull = ntiles - (ragged ? 1 : 0);
+  for (int t = 0; t < nfull; ++t) tile(t, std::false_type{});
+  if (ragged) tile(ntiles - 1, std::true_type{});
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     const float inv = vmax / 448.f / l_run[qb];

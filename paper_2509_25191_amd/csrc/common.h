@@ -39,6 +39,16 @@ __device__ __forceinline__ f32x16 mfma_fp8(i32x8 a, i32x8 b, f32x16 c) {
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// LDS swizzles (XOR on the 16-byte granule index of a tile row).  A
+// ds_read_b128 is served 16 consecutive lanes at a time from 64 four-byte
+// banks; with these swizzles 16 consecutive rows read at one logical granule
+// hit 16 distinct 16-byte bank groups, and so do the tile stores (ds_write_b64
+// of the FP8 V tile included, 32 lanes per pass).  Both depend on r mod 32
+// only, so the 32-row blocks of a tile share one lane address plus an
+// immediate offset.
+__device__ __forceinline__ int lds_swz8(int r) { return (r ^ ((r >> 3) & 3)) & 7; }  // 128-byte rows (8 granules)
+__device__ __forceinline__ int lds_swz4(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }  // 64-byte rows (4 granules)
+
 // Two float32 -> two E4M3 codes (round to nearest even) in the low 16 bits.
 // The hardware conversion turns magnitudes above 464 into NaN, so inputs are
 // clamped to +-448 first (saturating encode).

@@ -84,8 +84,8 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = (tid >> 3) + 32 * i, ch = tid & 7;
-      *(bf16x8*)&As[buf * BM * BK + r * BK + ((ch ^ (r & 7)) * 8)] = areg[i];
-      *(bf16x8*)&Ws[buf * BN * BK + r * BK + ((ch ^ (r & 7)) * 8)] = wreg[i];
+      *(bf16x8*)&As[buf * BM * BK + r * BK + ((ch ^ lds_swz8(r)) * 8)] = areg[i];
+      *(bf16x8*)&Ws[buf * BN * BK + r * BK + ((ch ^ lds_swz8(r)) * 8)] = wreg[i];
     }
   };
 
@@ -108,12 +108,12 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) {
         const int r = wm * 64 + mi * 32 + r32;
-        a[mi] = *(const bf16x8*)&As[buf * BM * BK + r * BK + (((2 * kk + g) ^ (r & 7)) * 8)];
+        a[mi] = *(const bf16x8*)&As[buf * BM * BK + r * BK + (((2 * kk + g) ^ lds_swz8(r)) * 8)];
       }
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) {
         const int r = wn * 64 + nj * 32 + r32;
-        b[nj] = *(const bf16x8*)&Ws[buf * BN * BK + r * BK + (((2 * kk + g) ^ (r & 7)) * 8)];
+        b[nj] = *(const bf16x8*)&Ws[buf * BN * BK + r * BK + (((2 * kk + g) ^ lds_swz8(r)) * 8)];
       }
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
