@@ -180,9 +180,10 @@ vggtx_status vggtx_quantize_fp8(vggtx_handle h, const void* x, vggtx_layout in_l
                                 uint8_t* codes, float* scales, void* stream);
 
 /* Attention autotuner.  Times every compiled tile variant of the attention
- * kernel for `prec` (VGGTX_BF16: 1 or 2 query blocks of 32 rows per wave;
- * VGGTX_FP8_E4M3: (query blocks per wave, waves per workgroup) in
- * {(1,4), (2,4), (1,8), (2,8)}) on synthetic Q, K, V written into the
+ * kernel for `prec` (VGGTX_BF16: variant 0 or 1 = 1 or 2 query blocks of
+ * 32 rows per wave, 4 waves; VGGTX_FP8_E4M3: variants 0..3 = (query blocks
+ * per wave, waves per workgroup) (1,4), (2,4), (1,8), (2,8)) on synthetic
+ * Q, K, V written into the
  * caller's workspace (one sequence of `n_tokens` tokens, 16 heads of 64; a
  * truncated problem of 8192 to 65536 tokens is representative since the kernels
  * are compute bound) and keeps the fastest in the handle for all later calls.

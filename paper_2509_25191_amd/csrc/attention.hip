@@ -49,6 +49,21 @@ __device__ __forceinline__ Item resolve_item(const SeqTable& t, int item, int ro
 }
 
 
+// max of 2 x 16 values as four chains of three-input maxima (v_max3_f32)
+__device__ __forceinline__ float max32(const f32x16& a, const f32x16& b) {
+  float m[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const f32x16& x = c < 2 ? a : b;
+    const int o = (c & 1) * 8;
+    float r = __builtin_fmaxf(__builtin_fmaxf(x[o], x[o + 1]), x[o + 2]);
+    r = __builtin_fmaxf(__builtin_fmaxf(r, x[o + 3]), x[o + 4]);
+    r = __builtin_fmaxf(__builtin_fmaxf(r, x[o + 5]), x[o + 6]);
+    m[c] = __builtin_fmaxf(r, x[o + 7]);
+  }
+  return __builtin_fmaxf(__builtin_fmaxf(__builtin_fmaxf(m[0], m[1]), m[2]), m[3]);
+}
+
 __device__ __forceinline__ float lane_swap_max(float v) {
   // v_permlane32_swap exchanges the two 32-lane halves of the wave
   auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
@@ -64,8 +79,8 @@ __device__ __forceinline__ float lane_swap_max(float v) {
 //                   stored in the order in which a lane's MFMA k-slots need
 //                   them (slot j of lane group g <-> key 8*(j/4) + 4*g + j%4),
 //                   granule ^ lds_swz8(d).
-template <int QB, bool OUT_F32>
-__global__ __launch_bounds__(256, 2) void attn_bf16_kernel(AttnParams p) {
+template <int QB, bool OUT_F32, int OCC>
+__global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
   constexpr int BN = 64, D = kHeadDim, BM = 128 * QB;
   __shared__ __attribute__((aligned(16))) bf16 Ks[2][BN * D];
   __shared__ __attribute__((aligned(16))) bf16 Vs[2][D * BN];
@@ -394,8 +409,8 @@ __device__ __forceinline__ int pack_e4m3x4(float e0, float e1, float e2, float e
 //      group g finds its 16 k-slots in one granule (slot j of group g <->
 //      key 32*(j/16) + 8*((j%16)/4) + 4*g + j%4), granules swizzled with
 //      lds_swz4(d).
-template <int QB, int NW>
-__global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
+template <int QB, int NW, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
   constexpr int BN = 64, D = kHeadDim, BM = 32 * QB * NW, NT = 64 * NW;
   __shared__ __attribute__((aligned(16))) uint8_t Ks[2][BN * D];
   __shared__ __attribute__((aligned(16))) uint8_t Vs[2][D * BN];
@@ -408,8 +423,7 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
   const uint8_t* K = (const uint8_t*)p.k + head * p.k_hs;
   const uint8_t* Vt = (const uint8_t*)p.vt + head * p.vt_hs + it.vb;
   const float* SQ = p.sq + head * p.sc_hs + it.bb;
-  const float* SK = p.sk + head * p.sc_hs + it.bb;
-  const float* SV = p.sv + head * p.sc_hs + it.bb;
+  const f32x4* KI = (const f32x4*)(p.kinfo + 4 * (head * p.sc_hs + it.bb));
   const float vmax = p.vmax[head];
 
   const i32x8 zero8 = {};
@@ -428,18 +442,31 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
   // K tile: 64 keys x 64 B; V tile: 64 d x 64 B; 512 granules of 16 B
   constexpr int LPT = 512 / NT;  // granules per thread
   i32x4 reg[LPT];
-  auto gload = [&](int kt) {
+  // granule gi of a tile: K (gi < 256) or V (gi >= 256), row (gi / 4) % 64,
+  // 16-byte chunk gi % 4; per-thread source of tile 0 and per-tile step
+  const uint8_t* src[LPT];
+  int64_t step[LPT];
+#pragma unroll
+  for (int i = 0; i < LPT; ++i) {
+    const int gi = tid + NT * i;
+    const int r = (gi >> 2) & 63, ch = gi & 3;
+    if (gi < 256) {
+      src[i] = K + (int64_t)(it.s0 + r) * p.k_ts + ch * 16;
+      step[i] = (int64_t)BN * p.k_ts;
+    } else {
+      src[i] = Vt + r * p.vt_ds + ch * 16;
+      step[i] = BN;
+    }
+  }
+  auto gload = [&](int t) {
     const i32x4 z = {};
+    const int rows_left = it.s1 - (it.s0 + t * BN);  // keys of this tile that exist
 #pragma unroll
     for (int i = 0; i < LPT; ++i) {
       const int gi = tid + NT * i;
-      const int isv = gi >> 8, r = (gi >> 2) & 63, ch = gi & 3;
-      if (!isv) {
-        const int key = kt + r;
-        reg[i] = key < it.s1 ? *(const i32x4*)(K + key * p.k_ts + ch * 16) : z;
-      } else {
-        reg[i] = *(const i32x4*)(Vt + r * p.vt_ds + (kt - it.s0) + ch * 16);
-      }
+      const int r = (gi >> 2) & 63;
+      const i32x4* a = (const i32x4*)(src[i] + t * step[i]);
+      reg[i] = (gi >= 256 || r < rows_left) ? *a : z;
     }
   };
   auto lstore = [&](int buf) {
@@ -470,7 +497,7 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
   }
   const float c2 = p.scale_log2;
   const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
-  gload(it.s0);
+  gload(0);
   lstore(0);
   __syncthreads();
   // One key tile; MASKED is set only for the final, partial tile of a
@@ -478,7 +505,7 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
   auto tile = [&](int t, auto masked) {
     constexpr bool MASKED = decltype(masked)::value;
     const int kt = it.s0 + t * BN, buf = t & 1;
-    if (t + 1 < ntiles) gload(kt + BN);
+    if (t + 1 < ntiles) gload(t + 1);
     i32x8 kf[2];
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
@@ -493,15 +520,13 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
       s[qb][0] = mfma_fp8(kf[0], qf[qb], f32x16{});
       s[qb][1] = mfma_fp8(kf[1], qf[qb], f32x16{});
     }
-    const int blk = (kt - it.s0) / kQuantRows;
-    const float sk = SK[blk];
-    const float rb = 448.f * SV[blk] / vmax;
-    const float lrb = __builtin_amdgcn_logf(rb);
-    const float inv_rb = 1.f / rb;
+    // key-block constants: s_k * c2, log2(r_b), 1 / r_b
+    const f32x4 ki = KI[(kt - it.s0) / kQuantRows];
+    const float lrb = ki[1], inv_rb = ki[2];
     i32x8 pw[QB];
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-      const float sigma = sq[qb] * sk * c2;
+      const float sigma = sq[qb] * ki[0];
       if (MASKED) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
@@ -509,15 +534,7 @@ __global__ __launch_bounds__(64 * NW, 2) void attn_fp8_kernel(AttnParams p) {
           for (int i = 0; i < 16; ++i)
             if (kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) s[qb][kb][i] = -INFINITY;
       }
-      float m4[4];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const f32x16& sv = s[qb][j >> 1];
-        const int o = (j & 1) * 8;
-        m4[j] = __builtin_fmaxf(__builtin_fmaxf(__builtin_fmaxf(sv[o], sv[o + 1]), __builtin_fmaxf(sv[o + 2], sv[o + 3])),
-                                __builtin_fmaxf(__builtin_fmaxf(sv[o + 4], sv[o + 5]), __builtin_fmaxf(sv[o + 6], sv[o + 7])));
-      }
-      const float mx = lane_swap_max(__builtin_fmaxf(__builtin_fmaxf(m4[0], m4[1]), __builtin_fmaxf(m4[2], m4[3])));
+      const float mx = lane_swap_max(max32(s[qb][0], s[qb][1]));
       const float m_new = __builtin_fmaxf(m_run[qb], mx * sigma);
       if (__any(m_new > m_run[qb])) {
         const float alpha = fast_exp2(m_run[qb] - m_new);
@@ -691,33 +708,62 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(const bf16* x, int64_t x
   }
 }
 
-__global__ void scale_max_kernel(const float* scales, int64_t sc_hs, int n_blocks, float* vmax) {
+__global__ void scale_max_kernel(const float* sk, const float* sv, int64_t sc_hs, int n_blocks, float c2,
+                                 float* vmax, float* kinfo) {
   const int head = blockIdx.x;
   float m = 0.f;
-  for (int i = threadIdx.x; i < n_blocks; i += 64) m = __builtin_fmaxf(m, scales[head * sc_hs + i]);
+  for (int i = threadIdx.x; i < n_blocks; i += 64) m = __builtin_fmaxf(m, sv[head * sc_hs + i]);
   m = wave_max(m);
   if (threadIdx.x == 0) vmax[head] = m;
+  for (int i = threadIdx.x; i < n_blocks; i += 64) {
+    const int64_t b = head * sc_hs + i;
+    const float r = 448.f * sv[b] / m;
+    const f32x4 ki = {sk[b] * c2, __builtin_amdgcn_logf(r), 1.f / r, 0.f};
+    *(f32x4*)(kinfo + 4 * b) = ki;
+  }
 }
 
 // ============================================================== launchers
+// Kernel variants: (32-row query blocks per wave, waves per workgroup, waves
+// per SIMD the register budget is sized for; the occupancy reached is set by
+// the registers actually used).  Every variant of one
+// precision performs the same per-row arithmetic in the same order, so they
+// agree bitwise; they differ in LDS reuse, register pressure and occupancy.
+struct AttnVariant {
+  int qb, nw, occ;
+};
+static const AttnVariant kBf16Variants[] = {{1, 4, 2}, {2, 4, 2}};
+static const AttnVariant kFp8Variants[] = {{1, 4, 2}, {2, 4, 2}, {1, 8, 2}, {2, 8, 2}};
+constexpr int kNumBf16Variants = sizeof(kBf16Variants) / sizeof(kBf16Variants[0]);
+constexpr int kNumFp8Variants = sizeof(kFp8Variants) / sizeof(kFp8Variants[0]);
+
+int attn_n_variants(int prec) {
+  if (prec == 1) return kNumBf16Variants;
+  if (prec == 2) return kNumFp8Variants;
+  return 1;
+}
+
 int attn_block_rows(int prec, int variant) {
-  if (prec == 1) return 128 * variant;                // BF16: query blocks per wave (1 or 2), 4 waves
-  if (prec == 2) {                                    // FP8 variants: (QB, waves) = (1,4) (2,4) (1,8) (2,8)
-    static const int rows[4] = {128, 256, 256, 512};
-    return rows[variant & 3];
-  }
+  if (prec == 1 && variant >= 0 && variant < kNumBf16Variants)
+    return 32 * kBf16Variants[variant].qb * kBf16Variants[variant].nw;
+  if (prec == 2 && variant >= 0 && variant < kNumFp8Variants)
+    return 32 * kFp8Variants[variant].qb * kFp8Variants[variant].nw;
   return 128;
 }
 
-hipError_t launch_attn_bf16(const AttnParams& p, int H, int qb, bool out_f32, hipStream_t s) {
-  dim3 grid(p.n_items, H), block(256);
-  if (qb == 1) {
-    if (out_f32) hipLaunchKernelGGL((attn_bf16_kernel<1, true>), grid, block, 0, s, p);
-    else hipLaunchKernelGGL((attn_bf16_kernel<1, false>), grid, block, 0, s, p);
-  } else {
-    if (out_f32) hipLaunchKernelGGL((attn_bf16_kernel<2, true>), grid, block, 0, s, p);
-    else hipLaunchKernelGGL((attn_bf16_kernel<2, false>), grid, block, 0, s, p);
+template <bool OUT_F32>
+static void launch_bf16_variant(const AttnParams& p, dim3 grid, int variant, hipStream_t s) {
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((attn_bf16_kernel<2, OUT_F32, 2>), grid, dim3(256), 0, s, p); break;
+    default: hipLaunchKernelGGL((attn_bf16_kernel<1, OUT_F32, 2>), grid, dim3(256), 0, s, p); break;
   }
+}
+
+hipError_t launch_attn_bf16(const AttnParams& p, int H, int variant, bool out_f32, hipStream_t s) {
+  if (variant < 0 || variant >= kNumBf16Variants) return hipErrorInvalidValue;
+  const dim3 grid(p.n_items, H);
+  if (out_f32) launch_bf16_variant<true>(p, grid, variant, s);
+  else launch_bf16_variant<false>(p, grid, variant, s);
   return hipGetLastError();
 }
 
@@ -727,12 +773,13 @@ hipError_t launch_attn_f32(const AttnParams& p, int H, hipStream_t s) {
 }
 
 hipError_t launch_attn_fp8(const AttnParams& p, int H, int variant, hipStream_t s) {
+  if (variant < 0 || variant >= kNumFp8Variants) return hipErrorInvalidValue;
   const dim3 grid(p.n_items, H);
   switch (variant) {
-    case 1: hipLaunchKernelGGL((attn_fp8_kernel<2, 4>), grid, dim3(256), 0, s, p); break;
-    case 2: hipLaunchKernelGGL((attn_fp8_kernel<1, 8>), grid, dim3(512), 0, s, p); break;
-    case 3: hipLaunchKernelGGL((attn_fp8_kernel<2, 8>), grid, dim3(512), 0, s, p); break;
-    default: hipLaunchKernelGGL((attn_fp8_kernel<1, 4>), grid, dim3(256), 0, s, p); break;
+    case 1: hipLaunchKernelGGL((attn_fp8_kernel<2, 4, 2>), grid, dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL((attn_fp8_kernel<1, 8, 2>), grid, dim3(512), 0, s, p); break;
+    case 3: hipLaunchKernelGGL((attn_fp8_kernel<2, 8, 2>), grid, dim3(512), 0, s, p); break;
+    default: hipLaunchKernelGGL((attn_fp8_kernel<1, 4, 2>), grid, dim3(256), 0, s, p); break;
   }
   return hipGetLastError();
 }
@@ -752,8 +799,9 @@ hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, uint8_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_scale_max(const float* scales, int64_t sc_hs, int n_blocks, float* vmax, int H, hipStream_t s) {
-  hipLaunchKernelGGL(scale_max_kernel, dim3(H), dim3(64), 0, s, scales, sc_hs, n_blocks, vmax);
+hipError_t launch_scale_max(const float* sk, const float* sv, int64_t sc_hs, int n_blocks, float c2, float* vmax,
+                            float* kinfo, int H, hipStream_t s) {
+  hipLaunchKernelGGL(scale_max_kernel, dim3(H), dim3(64), 0, s, sk, sv, sc_hs, n_blocks, c2, vmax, kinfo);
   return hipGetLastError();
 }
 

@@ -33,16 +33,18 @@ struct AttnParams {
   // FP8 scales: [H, n_blocks] (per-head stride sc_hs)
   const float* sq; const float* sk; const float* sv; int64_t sc_hs;
   const float* vmax;                     // FP8: per-head max of the V scales
+  const float* kinfo;                    // FP8: per (head, key block) constants, 4 floats each (launch_scale_max)
   float scale_log2;                      // log2(e) / sqrt(D)
   int n_items;                           // query tiles per head
   SeqTable seqs;
 };
 
 // ---- attention (attention.hip)
-hipError_t launch_attn_bf16(const AttnParams& p, int H, int qb_per_wave, bool out_f32, hipStream_t s);
+hipError_t launch_attn_bf16(const AttnParams& p, int H, int variant, bool out_f32, hipStream_t s);
 hipError_t launch_attn_f32(const AttnParams& p, int H, hipStream_t s);
 // FP8 variants: 0 = (1 query block per wave, 4 waves), 1 = (2, 4), 2 = (1, 8), 3 = (2, 8)
 hipError_t launch_attn_fp8(const AttnParams& p, int H, int variant, hipStream_t s);
+int attn_n_variants(int prec);              // kernel variants of a precision (1 = BF16, 2 = FP8)
 int attn_block_rows(int prec, int variant);  // query rows per work item of a kernel variant
 
 // Transposed, zero-padded copy of V: v [tokens, H, D] (bf16 or u8 codes) ->
@@ -56,8 +58,11 @@ hipError_t launch_v_transpose_bf16(const bf16* v, int64_t v_ts, int64_t v_hs, bf
 hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, uint8_t* codes, int64_t c_hs,
                             int64_t c_ds, bool transposed, float* scales, int64_t sc_hs,
                             const SeqTable& seqs, int n_blocks, int H, hipStream_t s);
-// per-head max over n_blocks scales -> vmax[H]
-hipError_t launch_scale_max(const float* scales, int64_t sc_hs, int n_blocks, float* vmax, int H, hipStream_t s);
+// Per-head max of the V block scales -> vmax[H], then the per key-block
+// constants of the FP8 attention kernel, kinfo[h][b] = {s_k * c2, log2(r),
+// 1 / r, 0} with r = 448 * s_v / vmax and c2 = log2(e) / sqrt(D).
+hipError_t launch_scale_max(const float* sk, const float* sv, int64_t sc_hs, int n_blocks, float c2, float* vmax,
+                            float* kinfo, int H, hipStream_t s);
 
 // ---- GEMMs (gemm.hip): C[M, N] = A[M, K] W[N, K]^T + bias, then an epilogue
 enum Epi { EPI_QKV = 0, EPI_RESID = 1, EPI_GELU = 2 };

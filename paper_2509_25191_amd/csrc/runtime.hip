@@ -39,8 +39,8 @@ struct vggtx_ctx {
   char arch[64];
   vggtx_config cfg;
   KernelTimer timer;
-  int attn_qb;      // BF16 attention: 32-row query blocks per wave (1 or 2)
-  int fp8_variant;  // FP8 attention tile variant (see launch_attn_fp8)
+  int bf16_variant;  // BF16 attention kernel variant (index into the BF16 variant table)
+  int fp8_variant;   // FP8 attention kernel variant (index into the FP8 variant table)
 };
 
 namespace {
@@ -205,6 +205,7 @@ struct Ws {
   float* sk = nullptr;
   float* sv = nullptr;
   float* vmax = nullptr;     // [H]
+  float* kinfo = nullptr;    // [H, nblk, 4]
   size_t total = 0;
 };
 
@@ -239,6 +240,7 @@ Ws carve(const vggtx_config& c, const WsShape& sh, vggtx_prec prec, char* base, 
     w.sk = (float*)take(H * sh.nblk * 4);
     w.sv = (float*)take(H * sh.nblk * 4);
     w.vmax = (float*)take(H * 4);
+    w.kinfo = (float*)take(H * sh.nblk * 16);
   }
   w.total = off;
   return w;
@@ -370,7 +372,7 @@ struct AttnIO {
   void* o; int64_t o_ts, o_hs;
   bf16* vt;
   uint8_t *q8, *k8, *v8t;
-  float *sq, *sk, *sv, *vmax;
+  float *sq, *sk, *sv, *vmax, *kinfo;
   int64_t npad;     // columns of vt / v8t
   int64_t nblk;     // per-head stride of the FP8 scale arrays
   int64_t n_tokens; // rows of the q8 / k8 code arrays
@@ -413,12 +415,14 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
                                           tn.second, H, st));
     }
     p.vt = io.vt;
-    // frames (P of order 10^3 tokens) keep 128-row work items to limit tail waste
-    const int qb = cls == VGGTX_K_ATTN_FRAME ? 1 : ctx->attn_qb;
-    for (auto& tn : make_tables(s, attn_block_rows(1, qb))) {
+    // frames (P of order 10^3 tokens) keep work items of at most 128 rows to
+    // limit tail waste
+    int var = ctx->bf16_variant;
+    if (cls == VGGTX_K_ATTN_FRAME && attn_block_rows(1, var) > 128) var = 0;
+    for (auto& tn : make_tables(s, attn_block_rows(1, var))) {
       p.seqs = tn.first; p.n_items = tn.second;
       Span sp(ctx, cls, table_flops(tn.first, H), st);
-      VGGTX_HIP(launch_attn_bf16(p, H, qb, false, st));
+      VGGTX_HIP(launch_attn_bf16(p, H, var, false, st));
     }
     return VGGTX_OK;
   }
@@ -433,12 +437,12 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
       VGGTX_HIP(launch_quant_fp8((const bf16*)io.v, io.v_ts, io.v_hs, io.v8t, (int64_t)kHeadDim * io.npad, io.npad,
                                  true, io.sv, io.nblk, tn.first, tn.second, H, st));
     }
-    VGGTX_HIP(launch_scale_max(io.sv, io.nblk, (int)s.scale_blocks(), io.vmax, H, st));
+    VGGTX_HIP(launch_scale_max(io.sk, io.sv, io.nblk, (int)s.scale_blocks(), p.scale_log2, io.vmax, io.kinfo, H, st));
   }
   p.q = io.q8; p.q_ts = kHeadDim; p.q_hs = N * kHeadDim;
   p.k = io.k8; p.k_ts = kHeadDim; p.k_hs = N * kHeadDim;
   p.vt = io.v8t;
-  p.sq = io.sq; p.sk = io.sk; p.sv = io.sv; p.sc_hs = io.nblk; p.vmax = io.vmax;
+  p.sq = io.sq; p.sk = io.sk; p.sv = io.sv; p.sc_hs = io.nblk; p.vmax = io.vmax; p.kinfo = io.kinfo;
   const int fv = ctx->fp8_variant;
   for (auto& tn : make_tables(s, attn_block_rows(2, fv))) {
     p.seqs = tn.first; p.n_items = tn.second;
@@ -461,7 +465,7 @@ vggtx_status attn_phase(const BlockRun& br, const Seqs& s, bool fp8, int64_t npa
   io.o = br.ws.o; io.o_ts = c.dim; io.o_hs = kHeadDim;
   io.vt = br.ws.vt;
   io.q8 = br.ws.q8; io.k8 = br.ws.k8; io.v8t = br.ws.v8t;
-  io.sq = br.ws.sq; io.sk = br.ws.sk; io.sv = br.ws.sv; io.vmax = br.ws.vmax;
+  io.sq = br.ws.sq; io.sk = br.ws.sk; io.sv = br.ws.sv; io.vmax = br.ws.vmax; io.kinfo = br.ws.kinfo;
   io.npad = npad; io.nblk = nblk; io.n_tokens = N;
   const vggtx_prec prec = br.prec == VGGTX_F32 ? VGGTX_F32 : (fp8 ? VGGTX_FP8_E4M3 : VGGTX_BF16);
   return run_attention(br.ctx, cls, io, s, c.heads, prec, br.stream);
@@ -612,6 +616,7 @@ Ws carve_attn(int H, int64_t N, int64_t npad, int64_t nblk, vggtx_prec prec, cha
     w.sk = (float*)take(H * nblk * 4);
     w.sv = (float*)take(H * nblk * 4);
     w.vmax = (float*)take(H * 4);
+    w.kinfo = (float*)take(H * nblk * 16);
   }
   w.total = off;
   return w;
@@ -648,7 +653,7 @@ vggtx_status attn_entry(vggtx_handle h, int cls, const void* q, const void* k, c
   io.o = o; io.o_ts = ol.token_stride; io.o_hs = ol.head_stride;
   io.vt = w.vt;
   io.q8 = w.q8; io.k8 = w.k8; io.v8t = w.v8t;
-  io.sq = w.sq; io.sk = w.sk; io.sv = w.sv; io.vmax = w.vmax;
+  io.sq = w.sq; io.sk = w.sk; io.sv = w.sv; io.vmax = w.vmax; io.kinfo = w.kinfo;
   io.npad = npad; io.nblk = nblk; io.n_tokens = N;
   return run_attention(h, cls, io, s, H, prec, (hipStream_t)stream);
 }
@@ -675,10 +680,16 @@ vggtx_status vggtx_create(vggtx_handle* h, int device, const vggtx_config* cfg) 
   snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
   c->cfg = *cfg;
   // defaults measured on MI355X (VGGT-L shapes); vggtx_autotune can re-pick them
-  c->attn_qb = 2;
-  if (const char* e = getenv("VGGTX_ATTN_QB")) c->attn_qb = (atoi(e) == 2) ? 2 : 1;
-  c->fp8_variant = 1;
-  if (const char* e = getenv("VGGTX_FP8_VARIANT")) c->fp8_variant = atoi(e) & 3;
+  c->bf16_variant = 1;
+  if (const char* e = getenv("VGGTX_BF16_VARIANT")) {
+    const int v = atoi(e);
+    if (v >= 0 && v < attn_n_variants(1)) c->bf16_variant = v;
+  }
+  c->fp8_variant = 2;
+  if (const char* e = getenv("VGGTX_FP8_VARIANT")) {
+    const int v = atoi(e);
+    if (v >= 0 && v < attn_n_variants(2)) c->fp8_variant = v;
+  }
   *h = c;
   return VGGTX_OK;
 }
@@ -806,10 +817,12 @@ namespace {
 
 constexpr int kTuneHeads = 16;
 
-int n_variants(vggtx_prec prec) { return prec == VGGTX_FP8_E4M3 ? 4 : (prec == VGGTX_BF16 ? 2 : 1); }
+int n_variants(vggtx_prec prec) {
+  return prec == VGGTX_FP8_E4M3 ? attn_n_variants(2) : (prec == VGGTX_BF16 ? attn_n_variants(1) : 1);
+}
 
 void set_variant(vggtx_ctx* c, vggtx_prec prec, int v) {
-  if (prec == VGGTX_BF16) c->attn_qb = v + 1;
+  if (prec == VGGTX_BF16) c->bf16_variant = v;
   if (prec == VGGTX_FP8_E4M3) c->fp8_variant = v;
 }
 
@@ -884,7 +897,7 @@ vggtx_status vggtx_autotune(vggtx_handle h, vggtx_prec prec, int n_tokens, void*
   hipEvent_t e0, e1;
   VGGTX_HIP(hipEventCreate(&e0));
   VGGTX_HIP(hipEventCreate(&e1));
-  const int saved_qb = h->attn_qb, saved_fv = h->fp8_variant;
+  const int saved_bv = h->bf16_variant, saved_fv = h->fp8_variant;
   const bool saved_timer = h->timer.enabled;
   h->timer.enabled = false;
   int best = 0;
@@ -913,7 +926,7 @@ vggtx_status vggtx_autotune(vggtx_handle h, vggtx_prec prec, int n_tokens, void*
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->timer.enabled = saved_timer;
-  h->attn_qb = saved_qb;
+  h->bf16_variant = saved_bv;
   h->fp8_variant = saved_fv;
   if (rc != VGGTX_OK) return rc;
   set_variant(h, prec, best);

@@ -181,7 +181,7 @@ def _handle_with(env):
 
 
 @pytest.mark.parametrize("prec,key,values", [(vg.FP8_E4M3, "VGGTX_FP8_VARIANT", [0, 1, 2, 3]),
-                                             (vg.BF16, "VGGTX_ATTN_QB", [1, 2])])
+                                             (vg.BF16, "VGGTX_BF16_VARIANT", [0, 1])])
 def test_tile_variants_are_bitwise_identical(prec, key, values):
     """Every tile variant computes each query row with the same arithmetic in the same order."""
     H, D = 16, 64
