@@ -170,8 +170,11 @@ vggtx_status vggtx_attn_global(vggtx_handle h, const void* q, const void* k, con
 /* FP8 E4M3 quantiser used by the FP8 global attention.  x: device bfloat16
  * [n_tokens, H, D] with layout `in_layout`.  For every head and every
  * 128-token block of every sequence (blocks start at each sequence start; the
- * last block of a sequence may be shorter): s = amax / 448 (1 when amax == 0)
- * and codes = RNE-saturate(x * (448 / amax)) in float32.
+ * last block of a sequence may be shorter): s = 2^e, e the smallest integer
+ * with amax <= 448 * 2^e (clamped to [-127, 127]; s = 1 when amax == 0), and
+ * codes = E4M3 round-to-nearest-even of x / s (exact scaling, so the E4M3
+ * rounding is the only one).  s is an OCP E8M0 block scale.  The attention
+ * path quantises Q after multiplying it by log2(e)/sqrt(D) in float32.
  *   codes  device uint8 [H, n_tokens, D]
  *   scales device float32 [H, n_blocks], n_blocks = sum_i ceil(len_i / 128),
  *          blocks numbered sequence by sequence. */

@@ -17,8 +17,9 @@ Parity status by function (what pins each one is listed in tests/test_oracle.py)
   layer_norm, gelu, linear, attention, block, aggregate, global_block_rows,
   frame_block_frames: pinned (closed forms, library routines, brute force,
   invariants).
-  e4m3_encode / e4m3_decode / quantize_rows: pinned (OCP FP8 definition,
-  exhaustive code table, torch.float8_e4m3fn).
+  e4m3_encode / e4m3_decode / quantize_rows / block_exponent: pinned (OCP FP8
+  definition, exhaustive code table, torch.float8_e4m3fn conversion of the
+  exactly scaled block, binade-edge exponents).
   attention_fp8_emulated: pinned by invariants (constant V gives that row
   exactly; error against the exact attention within the E4M3 bound).
   Agreement of the whole network with a trained VGGT: parity unpinned (no
@@ -29,4 +30,5 @@ from .aggregator import (  # noqa: F401
     attention_probs, block, aggregate, global_block_rows, frame_block_frames,
     frame_bounds, scene_bounds,
 )
-from .fp8 import e4m3_decode, e4m3_encode, quantize_rows, attention_fp8_emulated, E4M3_MAX  # noqa: F401
+from .fp8 import (e4m3_decode, e4m3_encode, quantize_rows, attention_fp8_emulated, block_exponent,  # noqa: F401
+                  logit_factor, E4M3_MAX)

@@ -391,18 +391,24 @@ __device__ __forceinline__ int pack_e4m3x4(float e0, float e1, float e2, float e
   return __builtin_amdgcn_cvt_pk_fp8_f32(e2, e3, lo, true);
 }
 
-// Global attention on OCP E4M3 operands (MFMA 32x32x64 f8f6f4, one MFMA per
-// 32x32 score block since K = D = 64).  Q, K and V carry one float32 scale
-// per 128-row block of their sequence; the K-block and Q-block scales and
-// log2(e)/sqrt(D) multiply the raw score in the exponent's FMA.  The V-block
-// scale is folded into the probabilities before they are rounded to E4M3:
-// A_j = p_j * 448 * s_v(block(j)) / vmax, where vmax is the largest V scale of
-// the head, so that one PV accumulator serves every key block and
-// O = (vmax / 448) * sum_j A_j V8_j / sum_j p_j.
+// Global attention on OCP E4M3 operands (MFMA 32x32x64 f8f6f4 with E8M0
+// block scales, one MFMA per 32x32 score block since K = D = 64).  Q, K and V
+// carry one power-of-two scale per 128-row block of their sequence, and Q was
+// quantised after multiplication by log2(e)/sqrt(D), so the scaled MFMA
+// yields base-2 logits directly: the Q- and K-block scales enter as the
+// instruction's E8M0 operands.  The accumulator input of the score MFMA is
+// log2(448) - m (m the running row maximum), so the MFMA result x is already
+// the exponent: p = 2^x <= 448 is the E4M3-ready probability, and the tile
+// needs no per-score multiply-add.  Only when a tile raises the maximum (and
+// on the first tile) are its scores shifted, the accumulator rescaled and the
+// accumulator input updated.
 //
-// The row sum l is taken from the same rounded A8 values that feed the PV
-// product (one extra MFMA against an all-ones operand), so the output stays
-// a convex combination of value rows whatever the rounding of P.
+// The V-block scale s_v(b) / vmax enters the P V MFMA as its E8M0 operand
+// for the V tile, so one PV accumulator serves every key block and
+// O = vmax * sum_j p8_j (s_v(j) / vmax) V8_j / sum_j p8_j.  The row sum is
+// taken from the same rounded p8 values that feed the PV product (one extra
+// MFMA against an all-ones operand), so the output stays a convex
+// combination of value rows whatever the rounding of P.
 //
 // LDS: Ks[key][d] bytes, 16-byte granules swizzled with lds_swz4(key);
 //      Vs[d][key'] bytes, keys of every 32-key block permuted so that lane
@@ -412,6 +418,7 @@ __device__ __forceinline__ int pack_e4m3x4(float e0, float e1, float e2, float e
 template <int QB, int NW, int OCC>
 __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
   constexpr int BN = 64, D = kHeadDim, BM = 32 * QB * NW, NT = 64 * NW;
+  constexpr float kLog2Max = 8.80735492205760410745f;  // log2(448)
   __shared__ __attribute__((aligned(16))) uint8_t Ks[2][BN * D];
   __shared__ __attribute__((aligned(16))) uint8_t Vs[2][D * BN];
 
@@ -423,20 +430,20 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
   const uint8_t* K = (const uint8_t*)p.k + head * p.k_hs;
   const uint8_t* Vt = (const uint8_t*)p.vt + head * p.vt_hs + it.vb;
   const float* SQ = p.sq + head * p.sc_hs + it.bb;
-  const f32x4* KI = (const f32x4*)(p.kinfo + 4 * (head * p.sc_hs + it.bb));
+  const i32x2* KI = (const i32x2*)(p.kinfo + 2 * (head * p.sc_hs + it.bb));
   const float vmax = p.vmax[head];
 
   const i32x8 zero8 = {};
   const int one4 = 0x38383838;  // four E4M3 1.0 codes
   const i32x8 ones8 = {one4, one4, one4, one4, one4, one4, one4, one4};
   i32x8 qf[QB];
-  float sq[QB];
+  int eq[QB];  // E8M0 code of the query block's scale
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     const int row = it.q0 + (wave * QB + qb) * 32 + r32;
     qf[qb] = row < it.s1 ? *(const i32x8*)(Q + row * p.q_ts + 32 * g) : zero8;
     // the 32 rows of a query block lie inside one 128-row scale block
-    sq[qb] = SQ[(it.q0 - it.s0 + (wave * QB + qb) * 32) / kQuantRows];
+    eq[qb] = (int)(__float_as_uint(SQ[(it.q0 - it.s0 + (wave * QB + qb) * 32) / kQuantRows]) >> 23);
   }
 
   // K tile: 64 keys x 64 B; V tile: 64 d x 64 B; 512 granules of 16 B
@@ -487,15 +494,16 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
   };
 
   f32x16 oacc[QB][2];
+  f32x16 cin[QB];  // accumulator input of the score MFMA: log2(448) - m, per query
   float m_run[QB], l_run[QB];
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     oacc[qb][0] = f32x16{};
     oacc[qb][1] = f32x16{};
-    m_run[qb] = -INFINITY;
+    cin[qb] = f32x16{};
+    m_run[qb] = kLog2Max;  // consistent with cin = 0; the first tile always shifts
     l_run[qb] = 0.f;
   }
-  const float c2 = p.scale_log2;
   const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
   gload(0);
   lstore(0);
@@ -514,19 +522,17 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
       const i32x4 hi = *(const i32x4*)&Ks[buf][r * D + (((2 * g + 1) ^ sw) * 16)];
       kf[kb] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
     }
+    // key-block E8M0 codes: K scale, V scale relative to vmax
+    const i32x2 ki = KI[(kt - it.s0) / kQuantRows];
     f32x16 s[QB][2];
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-      s[qb][0] = mfma_fp8(kf[0], qf[qb], f32x16{});
-      s[qb][1] = mfma_fp8(kf[1], qf[qb], f32x16{});
+      s[qb][0] = mfma_fp8_scaled(kf[0], qf[qb], cin[qb], ki[0], eq[qb]);
+      s[qb][1] = mfma_fp8_scaled(kf[1], qf[qb], cin[qb], ki[0], eq[qb]);
     }
-    // key-block constants: s_k * c2, log2(r_b), 1 / r_b
-    const f32x4 ki = KI[(kt - it.s0) / kQuantRows];
-    const float lrb = ki[1], inv_rb = ki[2];
     i32x8 pw[QB];
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-      const float sigma = sq[qb] * ki[0];
       if (MASKED) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
@@ -534,29 +540,29 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
           for (int i = 0; i < 16; ++i)
             if (kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) s[qb][kb][i] = -INFINITY;
       }
-      const float mx = lane_swap_max(max32(s[qb][0], s[qb][1]));
-      const float m_new = __builtin_fmaxf(m_run[qb], mx * sigma);
-      if (__any(m_new > m_run[qb])) {
-        const float alpha = fast_exp2(m_run[qb] - m_new);
+      const float xmax = lane_swap_max(max32(s[qb][0], s[qb][1]));
+      if (t == 0 || __any(xmax > kLog2Max)) {
+        // the first tile sets the maximum; later tiles only raise it
+        const float delta = t == 0 ? xmax - kLog2Max : __builtin_fmaxf(xmax - kLog2Max, 0.f);
+        const float alpha = fast_exp2(-delta);
         l_run[qb] *= alpha;
+        m_run[qb] += delta;
+        const float c = kLog2Max - m_run[qb];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           oacc[qb][0][i] *= alpha;
           oacc[qb][1][i] *= alpha;
+          s[qb][0][i] -= delta;
+          s[qb][1][i] -= delta;
+          cin[qb][i] = c;
         }
-        m_run[qb] = m_new;
       }
-      const float off = m_new - lrb;
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-        for (int i = 0; i < 16; i += 4) {
-          const float e0 = fast_exp2(__builtin_fmaf(s[qb][kb][i], sigma, -off));
-          const float e1 = fast_exp2(__builtin_fmaf(s[qb][kb][i + 1], sigma, -off));
-          const float e2 = fast_exp2(__builtin_fmaf(s[qb][kb][i + 2], sigma, -off));
-          const float e3 = fast_exp2(__builtin_fmaf(s[qb][kb][i + 3], sigma, -off));
-          pw[qb][(16 * kb + i) >> 2] = pack_e4m3x4(e0, e1, e2, e3);
-        }
+        for (int i = 0; i < 16; i += 4)
+          pw[qb][(16 * kb + i) >> 2] = pack_e4m3x4(fast_exp2(s[qb][kb][i]), fast_exp2(s[qb][kb][i + 1]),
+                                                   fast_exp2(s[qb][kb][i + 2]), fast_exp2(s[qb][kb][i + 3]));
     }
     i32x8 vf[2];
 #pragma unroll
@@ -569,9 +575,9 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
       const f32x16 lsum = mfma_fp8(ones8, pw[qb], f32x16{});
-      oacc[qb][0] = mfma_fp8(vf[0], pw[qb], oacc[qb][0]);
-      oacc[qb][1] = mfma_fp8(vf[1], pw[qb], oacc[qb][1]);
-      l_run[qb] = __builtin_fmaf(lsum[0], inv_rb, l_run[qb]);
+      oacc[qb][0] = mfma_fp8_scaled(vf[0], pw[qb], oacc[qb][0], ki[1], 127);
+      oacc[qb][1] = mfma_fp8_scaled(vf[1], pw[qb], oacc[qb][1], ki[1], 127);
+      l_run[qb] += lsum[0];
     }
     if (t + 1 < ntiles) {
       lstore(buf ^ 1);
@@ -584,7 +590,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
   if (ragged) tile(ntiles - 1, std::true_type{});
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
-    const float inv = vmax / 448.f / l_run[qb];
+    const float inv = vmax / l_run[qb];
     const int qrow = it.q0 + (wave * QB + qb) * 32 + r32;
     if (qrow < it.s1) {
 #pragma unroll
@@ -633,11 +639,31 @@ __global__ __launch_bounds__(256) void v_transpose_bf16_kernel(const bf16* v, in
 }
 
 // ============================================================== FP8 quantiser
-// One workgroup per (128-row scale block, head).  amax over the block's rows
-// and all D columns; s = amax / 448; codes = E4M3(x * (448 / amax)).
-__global__ __launch_bounds__(256) void quant_fp8_kernel(const bf16* x, int64_t x_ts, int64_t x_hs, uint8_t* codes,
-                                                        int64_t c_hs, int64_t c_ds, int transposed, float* scales,
-                                                        int64_t sc_hs, SeqTable seqs) {
+// Smallest integer e with amax <= 448 * 2^e, clamped to [-127, 127]; 0 for
+// amax = 0.  With amax = M * 2^A (M in [1, 2)): 448 * 2^e = 1.75 * 2^(e + 8),
+// so e = A - 8, plus one when M > 1.75 (mantissa field above 0x600000).
+__device__ __forceinline__ int block_exponent(float amax) {
+  if (!(amax > 0.f)) return 0;
+  const uint32_t b = __float_as_uint(amax);
+  const int ef = (int)(b >> 23);  // biased exponent; amax > 0, so no sign bit
+  if (ef == 0) return -127;       // subnormal amax: the clamp applies
+  const int e = ef - 127 - 8 + ((b & 0x7fffffu) > 0x600000u ? 1 : 0);
+  return e < -127 ? -127 : (e > 127 ? 127 : e);
+}
+
+// 2^e as a float for e in [-127, 127] (2^-127 is the subnormal 0x00400000).
+__device__ __forceinline__ float exp2i(int e) {
+  return e >= -126 ? __uint_as_float((uint32_t)(e + 127) << 23) : __uint_as_float(0x00400000u);
+}
+
+// One workgroup per (128-row scale block, head).  x' = x * pre (float32);
+// amax over the block's rows and all D columns; s = 2^e with
+// e = block_exponent(amax); codes = E4M3(x' / s), the division by a power of
+// two being exact.  s is stored as a float (an exact power of two, so its
+// exponent field is the OCP E8M0 code of the scale).
+__global__ __launch_bounds__(256) void quant_fp8_kernel(const bf16* x, int64_t x_ts, int64_t x_hs, float pre,
+                                                        uint8_t* codes, int64_t c_hs, int64_t c_ds, int transposed,
+                                                        float* scales, int64_t sc_hs, SeqTable seqs) {
   __shared__ float red[4];
   __shared__ uint8_t T[64][128 + 4];
   const int tid = threadIdx.x, head = blockIdx.y;
@@ -653,7 +679,7 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(const bf16* x, int64_t x
     bf16x8 t = {};
     if (valid) t = *(const bf16x8*)(X + row * x_ts + half * 32 + 8 * c);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[8 * c + j] = bf2f(t[j]);
+    for (int j = 0; j < 8; ++j) v[8 * c + j] = bf2f(t[j]) * pre;
   }
   float amax = 0.f;
 #pragma unroll
@@ -662,8 +688,9 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(const bf16* x, int64_t x
   if ((tid & 63) == 0) red[tid >> 6] = amax;
   __syncthreads();
   amax = __builtin_fmaxf(__builtin_fmaxf(red[0], red[1]), __builtin_fmaxf(red[2], red[3]));
-  const float inv = amax > 0.f ? 448.f / amax : 1.f;
-  if (tid == 0) scales[head * sc_hs + blk] = amax > 0.f ? amax / 448.f : 1.f;
+  const int ex = block_exponent(amax);
+  const float inv = exp2i(-ex);
+  if (tid == 0) scales[head * sc_hs + blk] = exp2i(ex);
   uint32_t w[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j)
@@ -708,18 +735,23 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(const bf16* x, int64_t x
   }
 }
 
-__global__ void scale_max_kernel(const float* sk, const float* sv, int64_t sc_hs, int n_blocks, float c2,
-                                 float* vmax, float* kinfo) {
+// Per head: vmax = the largest V block scale (a power of two), then the E8M0
+// codes the FP8 attention kernel hands to the matrix instructions, per key
+// block b: kinfo[b] = {E8M0(s_k(b)), E8M0(s_v(b) / vmax)} (the latter clamped
+// at 2^-127).  An exact power of two's float exponent field is its E8M0 code.
+__global__ void scale_max_kernel(const float* sk, const float* sv, int64_t sc_hs, int n_blocks, float* vmax,
+                                 int* kinfo) {
   const int head = blockIdx.x;
   float m = 0.f;
   for (int i = threadIdx.x; i < n_blocks; i += 64) m = __builtin_fmaxf(m, sv[head * sc_hs + i]);
   m = wave_max(m);
   if (threadIdx.x == 0) vmax[head] = m;
+  const int em = (int)(__float_as_uint(m) >> 23);
   for (int i = threadIdx.x; i < n_blocks; i += 64) {
     const int64_t b = head * sc_hs + i;
-    const float r = 448.f * sv[b] / m;
-    const f32x4 ki = {sk[b] * c2, __builtin_amdgcn_logf(r), 1.f / r, 0.f};
-    *(f32x4*)(kinfo + 4 * b) = ki;
+    const int ev = (int)(__float_as_uint(sv[b]) >> 23) - em + 127;
+    const i32x2 ki = {(int)(__float_as_uint(sk[b]) >> 23), ev < 0 ? 0 : ev};
+    *(i32x2*)(kinfo + 2 * b) = ki;
   }
 }
 
@@ -791,17 +823,17 @@ hipError_t launch_v_transpose_bf16(const bf16* v, int64_t v_ts, int64_t v_hs, bf
   return hipGetLastError();
 }
 
-hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, uint8_t* codes, int64_t c_hs, int64_t c_ds,
-                            bool transposed, float* scales, int64_t sc_hs, const SeqTable& seqs, int n_blocks, int H,
-                            hipStream_t s) {
-  hipLaunchKernelGGL(quant_fp8_kernel, dim3(n_blocks, H), dim3(256), 0, s, x, x_ts, x_hs, codes, c_hs, c_ds,
+hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, float pre, uint8_t* codes, int64_t c_hs,
+                            int64_t c_ds, bool transposed, float* scales, int64_t sc_hs, const SeqTable& seqs,
+                            int n_blocks, int H, hipStream_t s) {
+  hipLaunchKernelGGL(quant_fp8_kernel, dim3(n_blocks, H), dim3(256), 0, s, x, x_ts, x_hs, pre, codes, c_hs, c_ds,
                      transposed ? 1 : 0, scales, sc_hs, seqs);
   return hipGetLastError();
 }
 
-hipError_t launch_scale_max(const float* sk, const float* sv, int64_t sc_hs, int n_blocks, float c2, float* vmax,
-                            float* kinfo, int H, hipStream_t s) {
-  hipLaunchKernelGGL(scale_max_kernel, dim3(H), dim3(64), 0, s, sk, sv, sc_hs, n_blocks, c2, vmax, kinfo);
+hipError_t launch_scale_max(const float* sk, const float* sv, int64_t sc_hs, int n_blocks, float* vmax, int* kinfo,
+                            int H, hipStream_t s) {
+  hipLaunchKernelGGL(scale_max_kernel, dim3(H), dim3(64), 0, s, sk, sv, sc_hs, n_blocks, vmax, kinfo);
   return hipGetLastError();
 }
 

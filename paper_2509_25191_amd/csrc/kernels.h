@@ -33,7 +33,7 @@ struct AttnParams {
   // FP8 scales: [H, n_blocks] (per-head stride sc_hs)
   const float* sq; const float* sk; const float* sv; int64_t sc_hs;
   const float* vmax;                     // FP8: per-head max of the V scales
-  const float* kinfo;                    // FP8: per (head, key block) constants, 4 floats each (launch_scale_max)
+  const int* kinfo;                      // FP8: per (head, key block) E8M0 codes, 2 ints each (launch_scale_max)
   float scale_log2;                      // log2(e) / sqrt(D)
   int n_items;                           // query tiles per head
   SeqTable seqs;
@@ -52,17 +52,17 @@ int attn_block_rows(int prec, int variant);  // query rows per work item of a ke
 hipError_t launch_v_transpose_bf16(const bf16* v, int64_t v_ts, int64_t v_hs, bf16* vt, int64_t vt_hs,
                                    int64_t vt_ds, const SeqTable& seqs, int n_tiles, int H, hipStream_t s);
 
-// FP8 quantiser: x [tokens, H, D] bf16 -> codes and per-(head, 128-row block) scales.
+// FP8 quantiser: x [tokens, H, D] bf16, times the float32 factor `pre`, ->
+// codes and per-(head, 128-row block) power-of-two scales.
 // transposed == false: codes [H, tokens, D] (row-major, c_hs = tokens*D)
 // transposed == true:  codes [H, D, padded tokens] like vt above (zero padding).
-hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, uint8_t* codes, int64_t c_hs,
+hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, float pre, uint8_t* codes, int64_t c_hs,
                             int64_t c_ds, bool transposed, float* scales, int64_t sc_hs,
                             const SeqTable& seqs, int n_blocks, int H, hipStream_t s);
-// Per-head max of the V block scales -> vmax[H], then the per key-block
-// constants of the FP8 attention kernel, kinfo[h][b] = {s_k * c2, log2(r),
-// 1 / r, 0} with r = 448 * s_v / vmax and c2 = log2(e) / sqrt(D).
-hipError_t launch_scale_max(const float* sk, const float* sv, int64_t sc_hs, int n_blocks, float c2, float* vmax,
-                            float* kinfo, int H, hipStream_t s);
+// Per-head max of the V block scales -> vmax[H], then per key block b the
+// E8M0 codes kinfo[h][b] = {E8M0(s_k(b)), E8M0(s_v(b) / vmax[h])}.
+hipError_t launch_scale_max(const float* sk, const float* sv, int64_t sc_hs, int n_blocks, float* vmax, int* kinfo,
+                            int H, hipStream_t s);
 
 // ---- GEMMs (gemm.hip): C[M, N] = A[M, K] W[N, K]^T + bias, then an epilogue
 enum Epi { EPI_QKV = 0, EPI_RESID = 1, EPI_GELU = 2 };

@@ -205,7 +205,7 @@ struct Ws {
   float* sk = nullptr;
   float* sv = nullptr;
   float* vmax = nullptr;     // [H]
-  float* kinfo = nullptr;    // [H, nblk, 4]
+  int* kinfo = nullptr;      // [H, nblk, 2] E8M0 codes
   size_t total = 0;
 };
 
@@ -240,7 +240,7 @@ Ws carve(const vggtx_config& c, const WsShape& sh, vggtx_prec prec, char* base, 
     w.sk = (float*)take(H * sh.nblk * 4);
     w.sv = (float*)take(H * sh.nblk * 4);
     w.vmax = (float*)take(H * 4);
-    w.kinfo = (float*)take(H * sh.nblk * 16);
+    w.kinfo = (int*)take(H * sh.nblk * 8);
   }
   w.total = off;
   return w;
@@ -372,7 +372,8 @@ struct AttnIO {
   void* o; int64_t o_ts, o_hs;
   bf16* vt;
   uint8_t *q8, *k8, *v8t;
-  float *sq, *sk, *sv, *vmax, *kinfo;
+  float *sq, *sk, *sv, *vmax;
+  int* kinfo;
   int64_t npad;     // columns of vt / v8t
   int64_t nblk;     // per-head stride of the FP8 scale arrays
   int64_t n_tokens; // rows of the q8 / k8 code arrays
@@ -430,14 +431,15 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
   {
     Span sp(ctx, VGGTX_K_OTHER, 0.0, st);
     for (auto& tn : make_tables(s, kQuantRows)) {
-      VGGTX_HIP(launch_quant_fp8((const bf16*)io.q, io.q_ts, io.q_hs, io.q8, N * kHeadDim, 0, false, io.sq, io.nblk,
-                                 tn.first, tn.second, H, st));
-      VGGTX_HIP(launch_quant_fp8((const bf16*)io.k, io.k_ts, io.k_hs, io.k8, N * kHeadDim, 0, false, io.sk, io.nblk,
-                                 tn.first, tn.second, H, st));
-      VGGTX_HIP(launch_quant_fp8((const bf16*)io.v, io.v_ts, io.v_hs, io.v8t, (int64_t)kHeadDim * io.npad, io.npad,
-                                 true, io.sv, io.nblk, tn.first, tn.second, H, st));
+      // Q carries log2(e)/sqrt(D), so that the logits come out in base 2
+      VGGTX_HIP(launch_quant_fp8((const bf16*)io.q, io.q_ts, io.q_hs, p.scale_log2, io.q8, N * kHeadDim, 0, false,
+                                 io.sq, io.nblk, tn.first, tn.second, H, st));
+      VGGTX_HIP(launch_quant_fp8((const bf16*)io.k, io.k_ts, io.k_hs, 1.f, io.k8, N * kHeadDim, 0, false, io.sk,
+                                 io.nblk, tn.first, tn.second, H, st));
+      VGGTX_HIP(launch_quant_fp8((const bf16*)io.v, io.v_ts, io.v_hs, 1.f, io.v8t, (int64_t)kHeadDim * io.npad,
+                                 io.npad, true, io.sv, io.nblk, tn.first, tn.second, H, st));
     }
-    VGGTX_HIP(launch_scale_max(io.sk, io.sv, io.nblk, (int)s.scale_blocks(), p.scale_log2, io.vmax, io.kinfo, H, st));
+    VGGTX_HIP(launch_scale_max(io.sk, io.sv, io.nblk, (int)s.scale_blocks(), io.vmax, io.kinfo, H, st));
   }
   p.q = io.q8; p.q_ts = kHeadDim; p.q_hs = N * kHeadDim;
   p.k = io.k8; p.k_ts = kHeadDim; p.k_hs = N * kHeadDim;
@@ -616,7 +618,7 @@ Ws carve_attn(int H, int64_t N, int64_t npad, int64_t nblk, vggtx_prec prec, cha
     w.sk = (float*)take(H * nblk * 4);
     w.sv = (float*)take(H * nblk * 4);
     w.vmax = (float*)take(H * 4);
-    w.kinfo = (float*)take(H * nblk * 16);
+    w.kinfo = (int*)take(H * nblk * 8);
   }
   w.total = off;
   return w;
@@ -807,8 +809,8 @@ vggtx_status vggtx_quantize_fp8(vggtx_handle h, const void* x, vggtx_layout in_l
   const Seqs s = seqs_from_offsets(seq_offsets, n_seq, 1);
   const int64_t nblk = s.scale_blocks();
   for (auto& tn : make_tables(s, kQuantRows))
-    VGGTX_HIP(launch_quant_fp8((const bf16*)x, in_layout.token_stride, in_layout.head_stride, codes, N * kHeadDim, 0,
-                               false, scales, nblk, tn.first, tn.second, H, (hipStream_t)stream));
+    VGGTX_HIP(launch_quant_fp8((const bf16*)x, in_layout.token_stride, in_layout.head_stride, 1.f, codes,
+                               N * kHeadDim, 0, false, scales, nblk, tn.first, tn.second, H, (hipStream_t)stream));
   return VGGTX_OK;
 }
 

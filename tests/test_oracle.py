@@ -327,19 +327,42 @@ def test_e4m3_ties_to_even_and_saturation():
 def test_quantize_rows_scale_and_error_bound():
     rng = _rng(11)
     x = synth.round_bf16(rng.normal(0, 0.7, (300, 64)).astype(np.float32))
+    x[130:140] *= 37.0  # a block with a larger amax
     starts = np.array([0, 128, 256]); ends = np.array([128, 256, 300])
     codes, scales = oracle.quantize_rows(x, starts, ends)
     for i, (a, e) in enumerate(zip(starts, ends)):
-        amax = np.abs(x[a:e]).max()
-        assert scales[i] == np.float32(amax / np.float32(448))
+        amax = float(np.abs(x[a:e]).max())
+        # the scale is the smallest power of two with amax <= 448 s
+        ex = np.log2(float(scales[i]))
+        assert ex == np.round(ex) and 224.0 * scales[i] < amax <= 448.0 * scales[i]
+        # division by a power of two is exact: the codes are torch's own E4M3
+        # conversion of x / s (independent implementation)
+        ref = torch.from_numpy(x[a:e].astype(np.float64) / float(scales[i])).to(torch.float8_e4m3fn)
+        np.testing.assert_array_equal(codes[a:e], ref.view(torch.uint8).numpy())
         deq = oracle.e4m3_decode(codes[a:e]) * scales[i]
         # relative rounding error of E4M3 normals is at most 2^-4 (3 mantissa bits, RNE)
         err = np.abs(deq - x[a:e])
         bound = np.maximum(np.abs(x[a:e]) * 2.0 ** -4, 2.0 ** -10 * scales[i]) * (1 + 1e-6)
         assert (err <= bound).all()
-        assert (oracle.e4m3_decode(codes[a:e]).max() == 448.0) or (-oracle.e4m3_decode(codes[a:e]).min() == 448.0)
     z, s = oracle.quantize_rows(np.zeros((10, 4), np.float32), np.array([0]), np.array([10]))
     assert s[0] == 1.0 and (z == 0).all()
+    # pre-multiplied input: the float32 product is what gets quantised
+    c = oracle.logit_factor(64)
+    assert abs(float(c) - np.log2(np.e) / 8) < 1e-8
+    c1, s1 = oracle.quantize_rows(x, starts, ends, pre=c)
+    c2, s2 = oracle.quantize_rows((x * np.float32(c)).astype(np.float32), starts, ends)
+    np.testing.assert_array_equal(c1, c2)
+    np.testing.assert_array_equal(s1, s2)
+
+
+def test_block_exponent_edges():
+    be = oracle.block_exponent
+    assert be(448.0) == 0 and be(448.0 * 2.0 ** -3) == -3 and be(np.nextafter(np.float32(448), np.float32(1e9))) == 1
+    assert be(224.0) == -1 and be(np.nextafter(np.float32(224), np.float32(1e9))) == 0
+    assert be(1.0) == -8 and be(1.75) == -8 and be(np.nextafter(np.float32(1.75), np.float32(9))) == -7
+    assert be(0.0) == 0
+    assert be(1e-38) == -127            # clamped at the E8M0 minimum
+    assert be(3e38) == 120              # 3e38 / 448 lies in (2^119, 2^120]
 
 
 # ---------------------------------------------------------------- synth helpers
