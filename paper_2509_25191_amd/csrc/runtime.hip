@@ -687,7 +687,7 @@ vggtx_status vggtx_create(vggtx_handle* h, int device, const vggtx_config* cfg) 
     const int v = atoi(e);
     if (v >= 0 && v < attn_n_variants(1)) c->bf16_variant = v;
   }
-  c->fp8_variant = 2;
+  c->fp8_variant = 1;
   if (const char* e = getenv("VGGTX_FP8_VARIANT")) {
     const int v = atoi(e);
     if (v >= 0 && v < attn_n_variants(2)) c->fp8_variant = v;

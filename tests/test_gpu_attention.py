@@ -89,6 +89,20 @@ def test_attn_global_varlen_ragged(handle, prec):
         assert e < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3])
+def test_attn_global_single_key_tails(handle, prec):
+    """Sequences of 64k + 1 tokens: the last key tile holds one valid key and
+    the last query tile one valid row (waves with a single live query)."""
+    H, D = 4, 64
+    offs = [0, 65, 194, 387]
+    q, k, v = _qkv(H, offs[-1], D, "R0", seed=10, bf16=prec != vg.F32)
+    got = _run_global(handle, q, k, v, offs, prec)
+    ref = _oracle_seqs(q, k, v, offs)
+    e = max_abs_rel(got, ref)
+    print(f"single-key tails prec={prec} max_abs_rel={e:.3e}")
+    assert e < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", [vg.F32, vg.BF16])
 @pytest.mark.parametrize("S,P", [(8, 86), (3, 1374), (5, 1)])
 def test_attn_frame(handle, prec, S, P):
