@@ -16,6 +16,7 @@ the roofline of the dominant kernel and the FP64 oracle's throughput on the
 host CPU (extrapolated from a bounded sample).
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -35,6 +36,30 @@ PEAK_TFLOPS = {"fp8": 5000.0, "bf16": 2500.0, "f32": 157.3}  # MI355X dense MFMA
 PREC = {"fp8": vg.FP8_E4M3, "bf16": vg.BF16, "f32": vg.F32}
 P_TOKENS = 1374
 OUT_LAYERS = (4, 11, 17, 23)
+
+
+def measured_traffic(prec, S):
+    """HBM bytes per launch of the global-attention kernel at S=1000, from the
+    committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled
+    by the same counter's reading for a plain copy of known size).  None when
+    no summary exists for this workload or when it was taken on a different
+    attention source than the one built now."""
+    if S != 1000:
+        return None
+    path = os.path.join(ROOT, "profiles", f"attn_{prec}_kernel_vggt_l_s1000_traffic.txt")
+    src = os.path.join(ROOT, "paper_2509_25191_amd", "csrc", "attention.hip")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if kv.get("attention_hip_sha256") != digest or "hbm_bytes_per_launch" not in kv:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def log(msg):
@@ -139,6 +164,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the standalone BF16/FP32 attention rates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the run, copy 2 GiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
@@ -243,12 +270,19 @@ def main():
             "peak": PEAK_TFLOPS[args.prec],
             "unit": "TFLOP/s",
             "frac": (ga_tflops / PEAK_TFLOPS[args.prec]) if ga_tflops else None,
-            "traffic": None,
+            "traffic": measured_traffic(args.prec, S),
             "flops_per_launch": flops_per_launch,
             "avg_launch_ms": avg_ms,
             "launches": ga["launches"],
         },
     }
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.bfloat16, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy done: 2 GiB read, 2 GiB written")
+        del src, dst
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(S, P)
