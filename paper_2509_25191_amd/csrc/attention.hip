@@ -171,10 +171,16 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
         }
     }
 
-    // Phase 2: online softmax; probabilities packed as bf16 PV operands.
-    bf16x8 pb[QB][2][2];
+    bf16x8 vf[2][2][2];  // V fragments, read just before the first P V product
+
+    // Phase 2 per query block: online softmax, probabilities packed as bf16
+    // PV operands, then O^T += V^T P^T.  The softmax of block qb runs on the
+    // vector ALU while the matrix core still works on the score MFMAs of
+    // later blocks or the P V MFMAs of block qb-1 (scheduling fences keep
+    // this order).
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
+      if (QB > 1) __builtin_amdgcn_sched_barrier(0);
       if (MASKED) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
@@ -184,12 +190,7 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
             if (key >= it.s1) s[qb][kb][i] = -INFINITY;
           }
       }
-      float mx = s[qb][0][0];
-#pragma unroll
-      for (int i = 1; i < 16; ++i) mx = __builtin_fmaxf(mx, s[qb][0][i]);
-#pragma unroll
-      for (int i = 0; i < 16; ++i) mx = __builtin_fmaxf(mx, s[qb][1][i]);
-      mx = __builtin_fmaxf(mx, __shfl_xor(mx, 32));
+      const float mx = lane_swap_max(max32(s[qb][0], s[qb][1]));
       const float m_new = __builtin_fmaxf(m_run[qb], mx);
       if (__any(m_new > m_run[qb])) {
         const float alpha = fast_exp2((m_run[qb] - m_new) * c2);
@@ -203,38 +204,36 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
       }
       const float mc = m_new * c2;
       float ls = 0.f;
+      bf16x8 pb[2][2];
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           const float e = fast_exp2(__builtin_fmaf(s[qb][kb][i], c2, -mc));
           ls += e;
-          pb[qb][kb][i >> 3][i & 7] = f2bf(e);
+          pb[kb][i >> 3][i & 7] = f2bf(e);
         }
       l_run[qb] += ls;
-    }
-
-    // Phase 3: O^T += V^T P^T (V fragments live only here).
-    {
-      bf16x8 vf[2][2][2];
-#pragma unroll
-      for (int db = 0; db < 2; ++db)
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int d = db * 32 + r32;
-            vf[db][kb][h] = *(const bf16x8*)&Vs[buf][d * BN + (((2 * (2 * kb + h) + g) ^ lds_swz8(d)) * 8)];
-          }
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb)
+      if (qb == 0) {
 #pragma unroll
         for (int db = 0; db < 2; ++db)
 #pragma unroll
           for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) oacc[qb][db] = mfma_bf16(vf[db][kb][h], pb[qb][kb][h], oacc[qb][db]);
+            for (int h = 0; h < 2; ++h) {
+              const int d = db * 32 + r32;
+              vf[db][kb][h] = *(const bf16x8*)&Vs[buf][d * BN + (((2 * (2 * kb + h) + g) ^ lds_swz8(d)) * 8)];
+            }
+      }
+      if (QB > 1) __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) oacc[qb][db] = mfma_bf16(vf[db][kb][h], pb[kb][h], oacc[qb][db]);
     }
+    if (QB > 1) __builtin_amdgcn_sched_barrier(0);
 
     if (t + 1 < ntiles) {
       lstore(buf ^ 1);
@@ -530,9 +529,13 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
       s[qb][0] = mfma_fp8_scaled(kf[0], qf[qb], cin[qb], ki[0], eq[qb]);
       s[qb][1] = mfma_fp8_scaled(kf[1], qf[qb], cin[qb], ki[0], eq[qb]);
     }
-    i32x8 pw[QB];
+    i32x8 vf[2];  // V fragments, read just before the first P V product
+    // Query blocks in turn: the softmax of block qb runs on the vector ALU
+    // while the matrix core still works on the score MFMAs of later blocks or
+    // the P V MFMAs of block qb-1 (scheduling fences keep this order).
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
+      if (QB > 1) __builtin_amdgcn_sched_barrier(0);
       if (MASKED) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
@@ -557,28 +560,29 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
           cin[qb][i] = c;
         }
       }
+      i32x8 pw;
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
         for (int i = 0; i < 16; i += 4)
-          pw[qb][(16 * kb + i) >> 2] = pack_e4m3x4(fast_exp2(s[qb][kb][i]), fast_exp2(s[qb][kb][i + 1]),
-                                                   fast_exp2(s[qb][kb][i + 2]), fast_exp2(s[qb][kb][i + 3]));
-    }
-    i32x8 vf[2];
+          pw[(16 * kb + i) >> 2] = pack_e4m3x4(fast_exp2(s[qb][kb][i]), fast_exp2(s[qb][kb][i + 1]),
+                                               fast_exp2(s[qb][kb][i + 2]), fast_exp2(s[qb][kb][i + 3]));
+      if (qb == 0) {
 #pragma unroll
-    for (int db = 0; db < 2; ++db) {
-      const int d = db * 32 + r32, sw = lds_swz4(d);
-      const i32x4 lo = *(const i32x4*)&Vs[buf][d * BN + ((g ^ sw) * 16)];
-      const i32x4 hi = *(const i32x4*)&Vs[buf][d * BN + (((2 + g) ^ sw) * 16)];
-      vf[db] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-    }
-#pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-      const f32x16 lsum = mfma_fp8(ones8, pw[qb], f32x16{});
-      oacc[qb][0] = mfma_fp8_scaled(vf[0], pw[qb], oacc[qb][0], ki[1], 127);
-      oacc[qb][1] = mfma_fp8_scaled(vf[1], pw[qb], oacc[qb][1], ki[1], 127);
+        for (int db = 0; db < 2; ++db) {
+          const int d = db * 32 + r32, sw = lds_swz4(d);
+          const i32x4 lo = *(const i32x4*)&Vs[buf][d * BN + ((g ^ sw) * 16)];
+          const i32x4 hi = *(const i32x4*)&Vs[buf][d * BN + (((2 + g) ^ sw) * 16)];
+          vf[db] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        }
+      }
+      if (QB > 1) __builtin_amdgcn_sched_barrier(0);
+      const f32x16 lsum = mfma_fp8(ones8, pw, f32x16{});
+      oacc[qb][0] = mfma_fp8_scaled(vf[0], pw, oacc[qb][0], ki[1], 127);
+      oacc[qb][1] = mfma_fp8_scaled(vf[1], pw, oacc[qb][1], ki[1], 127);
       l_run[qb] += lsum[0];
     }
+    if (QB > 1) __builtin_amdgcn_sched_barrier(0);
     if (t + 1 < ntiles) {
       lstore(buf ^ 1);
       __syncthreads();
