@@ -108,9 +108,10 @@ def attn_only_rate(h, S, prec, dev, gen):
 
 def cpu_baseline(S, P, C=1024, H=16, F=4096, depth=24):
     """FP64 oracle throughput on the host, extrapolated to the whole forward
-    from timed pieces: one frame block on one frame; the token-local part of
-    a block (LN, QKV, out-projection, MLP) on a 2048-row slab; global
-    attention of 32 query rows of one head against all S*P keys."""
+    from timed pieces (about 10 s of CPU work): the frame block on 4 frames;
+    the token-local part of a block (LN, QKV, out-projection, MLP) on a
+    16384-row slab; global attention of 512 query rows of one head against
+    all S*P keys."""
     import threadpoolctl
 
     import oracle
@@ -118,7 +119,8 @@ def cpu_baseline(S, P, C=1024, H=16, F=4096, depth=24):
     N = S * P
     w = synth.gen_block(rng, C, F)
     w64 = {k: v.astype(np.float64) for k, v in w.items()}
-    x1 = rng.standard_normal((P, C))
+    nf = 4
+    x1 = rng.standard_normal((nf * P, C))
 
     def best(fn, reps=2):
         ts = []
@@ -126,8 +128,8 @@ def cpu_baseline(S, P, C=1024, H=16, F=4096, depth=24):
             t0 = time.perf_counter(); fn(); ts.append(time.perf_counter() - t0)
         return min(ts)
 
-    t_frame = best(lambda: oracle.block(x1, w64, [(0, P)], H, 1e-6))
-    rows = 2048
+    t_frame = best(lambda: oracle.block(x1, w64, [(f * P, (f + 1) * P) for f in range(nf)], H, 1e-6)) / nf
+    rows = 16384
     xs = rng.standard_normal((rows, C))
 
     def token_local():
@@ -138,7 +140,7 @@ def cpu_baseline(S, P, C=1024, H=16, F=4096, depth=24):
         oracle.linear(oracle.gelu(oracle.linear(h2, w64["w_fc1"], w64["b_fc1"])), w64["w_fc2"], w64["b_fc2"])
 
     t_tok = best(token_local)
-    qrows = 32
+    qrows = 512
     q = rng.standard_normal((1, qrows, 64))
     k = rng.standard_normal((1, N, 64))
     v = rng.standard_normal((1, N, 64))
@@ -147,7 +149,7 @@ def cpu_baseline(S, P, C=1024, H=16, F=4096, depth=24):
     total = depth * per_layer
     info = threadpoolctl.threadpool_info()
     cores = max([i.get("num_threads", 1) for i in info] + [1])
-    sample = (f"oracle pieces timed: frame block on 1 frame of {P} tokens ({t_frame:.2f}s), token-local block "
+    sample = (f"oracle pieces timed: frame block on {nf} frames of {P} tokens ({nf * t_frame:.2f}s), token-local block "
               f"ops on {rows} rows ({t_tok:.2f}s), global attention of {qrows} query rows x 1 head over {N} keys "
               f"({t_att:.2f}s); extrapolated x{S} frames, x{N / rows:.0f} slabs, x{N * H / qrows:.0f} row groups, "
               f"x{depth} layers = {total:.3g}s per forward")
