@@ -7,6 +7,8 @@
   (teacher forcing); the frame half on 4 frames against the FP64 frame block
   fed with the previous layer's global output.  This measures each layer's
   local error; the whole-network drift is covered at small sizes.
+* Layer 0 of the S=1000 configuration (1,374,000 global tokens, FP8 global
+  attention), teacher-forced the same way.
 * Global attention at S=1000 frames (1,374,000 tokens) in BF16 and FP8, and
   over the 12-scene varlen batch, in the launch configuration the benchmark
   times; the oracle evaluates sampled query rows against all keys.
@@ -125,3 +127,38 @@ def test_attn_global_varlen_12_scenes_sampled_rows():
     print(f"varlen 12 scenes ({frames}) max_abs_rel = {worst:.3e}")
     assert worst < 2e-2
     h.close()
+
+
+def test_aggregate_vggt_l_s1000_layer0_fp8():
+    """Layer 0 of the S=1000 configuration (1,374,000 global tokens) with FP8
+    global attention, in the benchmark's launch configuration: the global half
+    on 256 sampled rows against the FP64 global block fed with the GPU's frame
+    output, the frame half on 4 frames against the FP64 frame block of the
+    input tokens."""
+    m = synth.ModelConfig()
+    S = 1000
+    N = S * P
+    C = m.dim
+    rng = np.random.default_rng(1000)
+    tokens = rng.standard_normal((S, P, C), dtype=np.float32)
+    lw = {"frame": synth.gen_block(rng, C, m.mlp_hidden, bf16=True),
+          "global": synth.gen_block(rng, C, m.mlp_hidden, bf16=True)}
+    h = vg.Handle(0, dim=C, heads=m.heads, mlp_hidden=m.mlp_hidden)
+    out = vg.aggregate(h.h, to_dev(tokens, torch.float32), _bf16_weights_dev([lw]), [0], vg.FP8_E4M3,
+                       out_dtype=vg.OUT_F32)
+    torch.cuda.synchronize()
+    frames = [0, S - 1, 7, 519]
+    got_f = out[0, frames, :, :C].cpu().numpy()
+    ref_f = oracle.frame_block_frames(tokens.reshape(N, C)[: (max(frames) + 1) * P].astype(np.float64),
+                                      lw["frame"], frames, P, m.heads, m.ln_eps)
+    ef = max_abs_rel(got_f, ref_f)
+    del ref_f
+    rows = synth.sample_rows(1000, N, 256, P)
+    go_rows = out[0, :, :, C:].reshape(N, C)[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    fo = out[0, :, :, :C].reshape(N, C).cpu().numpy()
+    del out
+    h.close()
+    ref_g = oracle.global_block_rows(fo, lw["global"], rows, m.heads, m.ln_eps)
+    eg = max_abs_rel(go_rows, ref_g)
+    print(f"S=1000 FP8 layer 0: frame half {ef:.3e}  global half {eg:.3e}", flush=True)
+    assert ef < 2e-2 and eg < 6e-2
