@@ -3,14 +3,15 @@
 // FP8 E4M3 quantiser that feed it.
 //
 // Every kernel computes, per sequence and head, O = softmax(Q K^T / sqrt(D)) V
-// without storing the score matrix: keys are visited in tiles, a running row
-// maximum m and row sum l are kept in float32 and the partial output is
-// rescaled by 2^((m_old - m_new) * log2(e)/sqrt(D)) whenever m grows.
+// without storing the score matrix: keys are visited in tiles of 64, a
+// running row maximum m and row sum l are kept in float32 and the partial
+// output is rescaled by 2^(m_old - m_new) (logits in base 2) whenever m
+// grows.
 //
-// Work decomposition: one workgroup (4 waves) per (query tile, head).  The
-// query tile of a wave is 32*QB rows; scores are computed transposed,
-// S^T = K Q^T, so that every lane owns one query column of the MFMA
-// accumulator.  That makes the softmax statistics lane-local (plus one
+// Work decomposition: one workgroup (4 or 8 waves, per kernel variant) per
+// (query tile, head); a wave owns 32*QB query rows.  Scores are computed
+// transposed, S^T = K Q^T, so that every lane owns one query column of the
+// MFMA accumulator.  That makes the softmax statistics lane-local (plus one
 // exchange with lane l^32) and lets the probabilities feed the P V product
 // (O^T = V^T P^T) straight from registers.
 #include <type_traits>
@@ -104,14 +105,25 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
       qf[qb][c] = row < it.s1 ? *(const bf16x8*)(Q + row * p.q_ts + 16 * c + 8 * g) : zero8;
   }
 
+  // K and V tile rows (tid / 8) + 32 i, 16-byte chunk tid % 8: per-thread
+  // sources of tile 0, advanced by one tile per step
   bf16x8 kreg[2], vreg[2];
-  auto gload = [&](int kt) {
+  const bf16* ksrc[2];
+  const bf16* vsrc[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int r = (tid >> 3) + 32 * i, ch = tid & 7;
+    ksrc[i] = K + (int64_t)(it.s0 + r) * p.k_ts + ch * 8;
+    vsrc[i] = Vt + r * p.vt_ds + ch * 8;
+  }
+  const int64_t kstep = (int64_t)BN * p.k_ts;
+  auto gload = [&](int t) {
+    const int rows_left = it.s1 - (it.s0 + t * BN);  // keys of this tile that exist
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      const int r = (tid >> 3) + 32 * i, ch = tid & 7;
-      const int key = kt + r;
-      kreg[i] = key < it.s1 ? *(const bf16x8*)(K + key * p.k_ts + ch * 8) : zero8;
-      vreg[i] = *(const bf16x8*)(Vt + r * p.vt_ds + (kt - it.s0) + ch * 8);
+      const int r = (tid >> 3) + 32 * i;
+      kreg[i] = r < rows_left ? *(const bf16x8*)(ksrc[i] + t * kstep) : zero8;
+      vreg[i] = *(const bf16x8*)(vsrc[i] + t * BN);
     }
   };
   auto lstore = [&](int buf) {
@@ -139,7 +151,7 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
   const float c2 = p.scale_log2;
   const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
 
-  gload(it.s0);
+  gload(0);
   lstore(0);
   __syncthreads();
 
@@ -148,7 +160,7 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
   auto tile = [&](int t, auto masked) {
     constexpr bool MASKED = decltype(masked)::value;
     const int kt = it.s0 + t * BN, buf = t & 1;
-    if (t + 1 < ntiles) gload(kt + BN);
+    if (t + 1 < ntiles) gload(t + 1);
 
     // Phase 1: scores of every query block (K fragments live only here).
     f32x16 s[QB][2];
