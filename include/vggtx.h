@@ -33,7 +33,8 @@
  *     GEMMs and attention on bfloat16 operands with float32 accumulation, float32
  *     softmax statistics and a float32 residual stream.  VGGTX_FP8_E4M3 is
  *     VGGTX_BF16 with global attention computed on OCP FP8 E4M3 Q, K, V and
- *     probabilities with per-128-row-block float32 scales.
+ *     probabilities, with one power-of-two (OCP E8M0) scale per 128-row block
+ *     of each sequence (see vggtx_quantize_fp8).
  */
 #ifndef VGGTX_H
 #define VGGTX_H
