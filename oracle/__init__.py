@@ -22,6 +22,9 @@ Parity status by function (what pins each one is listed in tests/test_oracle.py)
   exactly scaled block, binade-edge exponents).
   attention_fp8_emulated: pinned by invariants (constant V gives that row
   exactly; error against the exact attention within the E4M3 bound).
+  patchify, frame_tokens, embed (the patch-embedding front end): pinned
+  (patch embedding against a float64 Conv2d and a brute-force loop, depth-0
+  closed form, frame permutation and scene-first token rules).
   Agreement of the whole network with a trained VGGT: parity unpinned (no
   trained weights or worked numeric example exist for this path).
 """
@@ -32,3 +35,4 @@ from .aggregator import (  # noqa: F401
 )
 from .fp8 import (e4m3_decode, e4m3_encode, quantize_rows, attention_fp8_emulated, block_exponent,  # noqa: F401
                   logit_factor, E4M3_MAX)
+from .embed import patchify, frame_tokens, embed  # noqa: F401

@@ -183,3 +183,42 @@ def sample_rows(seed: int, n_rows: int, n_sample: int, P: int, extra: Sequence[i
     pool = np.setdiff1d(np.arange(n_rows), forced)
     draw = rng.choice(pool, size=min(need, len(pool)), replace=False) if need else np.array([], int)
     return np.sort(np.concatenate([np.array(forced, dtype=np.int64), draw.astype(np.int64)]))
+
+
+# --------------------------------------------------------------------------
+# patch-embedding front end (images -> aggregator input tokens)
+# --------------------------------------------------------------------------
+
+EMBED_PATCH = 14      # patch side in pixels
+EMBED_SPECIAL = 5     # 1 class / camera token + 4 register tokens per frame
+
+
+def gen_images(rng: np.random.Generator, S: int, height: int, width: int) -> np.ndarray:
+    """Normalised images, float32 N(0, 1), shape [S, 3, height, width]."""
+    return rng.standard_normal((S, 3, height, width), dtype=np.float32)
+
+
+def gen_embed(rng: np.random.Generator, model: ModelConfig, height: int, width: int, depth: int,
+              std: float = 0.02, bf16: bool = False) -> Dict[str, object]:
+    """Front-end parameters, drawn in this order: w_patch [C, 3*14*14] (the
+    Conv2d weight [C, 3, 14, 14] flattened), b_patch [C], pos [1 + n_patches, C],
+    cls [C], reg [4, C], then ``depth`` blocks (``gen_block``), norm_g, norm_b
+    [C], cam [2, C], agg_reg [2, 4, C].  All N(0, std) except norm_g = 1 + N(0, std)."""
+    C = model.dim
+    n_patch = (height // EMBED_PATCH) * (width // EMBED_PATCH)
+    def draw(shape, one=False):
+        v = rng.normal(0.0, std, size=shape) + (1.0 if one else 0.0)
+        v = v.astype(np.float32)
+        return round_bf16(v) if bf16 else v
+    w: Dict[str, object] = {}
+    w["w_patch"] = draw((C, 3 * EMBED_PATCH * EMBED_PATCH))
+    w["b_patch"] = draw((C,))
+    w["pos"] = draw((1 + n_patch, C))
+    w["cls"] = draw((C,))
+    w["reg"] = draw((EMBED_SPECIAL - 1, C))
+    w["blocks"] = [gen_block(rng, C, model.mlp_hidden, std=std, bf16=bf16) for _ in range(depth)]
+    w["norm_g"] = draw((C,), one=True)
+    w["norm_b"] = draw((C,))
+    w["cam"] = draw((2, C))
+    w["agg_reg"] = draw((2, EMBED_SPECIAL - 1, C))
+    return w
