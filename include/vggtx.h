@@ -201,6 +201,55 @@ vggtx_status vggtx_autotune_workspace_size(vggtx_handle h, int n_tokens, size_t*
 vggtx_status vggtx_autotune(vggtx_handle h, vggtx_prec prec, int n_tokens, void* ws, size_t ws_bytes, void* stream,
                             int* chosen);
 
+/* ---------------------------------------------------------------- front end
+ * Per-frame patch embedding (Sec. 3.2: every frame first goes through a
+ * DINO-based patch-embedding extractor; it is intra-frame, so frames are
+ * processed in chunks of `frame_chunk`, at most 2048, without changing the
+ * result).  The extractor is not described in the paper; the reading built
+ * here is a DINO-style ViT:
+ *   patches  non-overlapping 14 x 14 pixel patches, numbered row-major over
+ *            the (height/14) x (width/14) grid; patch vector entry
+ *            c*196 + ky*14 + kx = pixel (c, 14*py + ky, 14*px + kx)
+ *   tokens   per frame [class + pos[0], reg[0..3], W_patch p_i + b_patch +
+ *            pos[1 + i] for every patch i]  (Pd = 5 + n_patches tokens)
+ *   blocks   `depth` blocks of the aggregator's kind, attention over the Pd
+ *            tokens of one frame, then a final LayerNorm (norm_g, norm_b)
+ *   output   the aggregator input: per frame [cam[s], agg_reg[s][0..3], the
+ *            normalised patch tokens], s = 0 for the first frame of a scene
+ *            and 1 for the others (P = Pd tokens per frame).
+ * A LayerScale on a block's residual branches, if a model has one, is folded
+ * into that block's w_o / b_o and w_fc2 / b_fc2 rows by the caller.
+ *
+ * Device pointers, float32 for VGGTX_F32 and bfloat16 otherwise:
+ *   w_patch [C, 588] (a Conv2d weight [C, 3, 14, 14] flattened), b_patch [C],
+ *   pos [1 + n_patches, C], cls [C], reg [4, C], norm_g / norm_b [C],
+ *   cam [2, C], agg_reg [2, 4, C]; blocks: host array [depth] (may be null
+ *   when depth == 0). */
+typedef struct {
+  const void *w_patch, *b_patch, *pos, *cls, *reg;
+  const vggtx_block_w* blocks;
+  int depth;
+  const void *norm_g, *norm_b, *cam, *agg_reg;
+} vggtx_embed_w;
+
+/* Workspace bytes vggtx_embed needs for `total_frames` frames of
+ * height x width pixels (it holds one chunk of frames, not all of them). */
+vggtx_status vggtx_embed_workspace_size(vggtx_handle h, int total_frames, int height, int width, vggtx_prec prec,
+                                        size_t* bytes);
+
+/* Front end over the frames of n_scenes scenes stored back to back:
+ *   images        device float32 [S, 3, height, width] (normalised pixels);
+ *                 height and width positive multiples of 14
+ *   frame_offsets host int32 [n_scenes + 1], frame_offsets[0] == 0,
+ *                 non-decreasing, S = frame_offsets[n_scenes]
+ *   tokens        device float32 [S, 5 + n_patches, C], written in full
+ * VGGTX_BF16 runs the blocks as in the aggregator (bfloat16 operands, float32
+ * residual); VGGTX_FP8_E4M3 behaves as VGGTX_BF16 here (the front end has no
+ * global attention); VGGTX_F32 runs in float32. */
+vggtx_status vggtx_embed(vggtx_handle h, const float* images, int height, int width,
+                         const int32_t* frame_offsets, int n_scenes, const vggtx_embed_w* w,
+                         float* tokens, vggtx_prec prec, void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel timing (tracing).  While enabled, every kernel launch of the classes
  * below is bracketed by a pair of HIP events recorded on its launch stream, and
  * vggtx_timing_read() waits for those events and returns, per class, the summed

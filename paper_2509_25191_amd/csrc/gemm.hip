@@ -3,6 +3,8 @@
 //   EPI_RESID x += y W^T + b in place (attention out-projection and second MLP
 //             Linear), optionally copying the new residual into an output slot
 //   EPI_GELU  hidden = GELU(h W_1^T + b_1) with the exact-erf GELU
+//   EPI_EMBED patch tokens = patches W_patch^T + b + position embedding,
+//             scattered into the token rows behind each frame's special tokens
 // C[M, N] = A[M, K] W[N, K]^T: both operands are K-contiguous ("NT"), which is
 // the natural operand order of the MFMA (8 consecutive k per lane).
 #include "common.h"
@@ -44,6 +46,14 @@ __device__ __forceinline__ void epi4(const GemmParams& p, int r, int col, float 
       if (p.out_f32) st4<float>((float*)p.out + grow * p.ldo + col, nv);
       else st4<bf16>((bf16*)p.out + grow * p.ldo + col, nv);
     }
+  } else if (EPI == EPI_EMBED) {
+    const int64_t f = grow / p.emb_np;
+    const int i = (int)(grow - f * p.emb_np);
+    const T* pos = (const T*)p.pos + (int64_t)(1 + i) * p.N + col;
+    float nv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) nv[j] = v[j] + ldf(pos + j);
+    st4<float>(p.x + (f * p.emb_pd + kEmbedSpecial + i) * p.ldx + col, nv);
   } else {
     float gv[4] = {gelu_erf(v[0]), gelu_erf(v[1]), gelu_erf(v[2]), gelu_erf(v[3])};
     st4<T>((T*)p.hid + (int64_t)r * p.ldh + col, gv);
@@ -192,6 +202,7 @@ hipError_t launch_gemm_bf16(const GemmParams& p, Epi epi, hipStream_t s) {
     case EPI_QKV: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_QKV>, grid, block, 0, s, p); break;
     case EPI_RESID: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_RESID>, grid, block, 0, s, p); break;
     case EPI_GELU: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_GELU>, grid, block, 0, s, p); break;
+    case EPI_EMBED: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_EMBED>, grid, block, 0, s, p); break;
   }
   return hipGetLastError();
 }
@@ -202,6 +213,7 @@ hipError_t launch_gemm_f32(const GemmParams& p, Epi epi, hipStream_t s) {
     case EPI_QKV: hipLaunchKernelGGL(gemm_f32_kernel<EPI_QKV>, grid, block, 0, s, p); break;
     case EPI_RESID: hipLaunchKernelGGL(gemm_f32_kernel<EPI_RESID>, grid, block, 0, s, p); break;
     case EPI_GELU: hipLaunchKernelGGL(gemm_f32_kernel<EPI_GELU>, grid, block, 0, s, p); break;
+    case EPI_EMBED: hipLaunchKernelGGL(gemm_f32_kernel<EPI_EMBED>, grid, block, 0, s, p); break;
   }
   return hipGetLastError();
 }

@@ -65,7 +65,7 @@ hipError_t launch_scale_max(const float* sk, const float* sv, int64_t sc_hs, int
                             int H, hipStream_t s);
 
 // ---- GEMMs (gemm.hip): C[M, N] = A[M, K] W[N, K]^T + bias, then an epilogue
-enum Epi { EPI_QKV = 0, EPI_RESID = 1, EPI_GELU = 2 };
+enum Epi { EPI_QKV = 0, EPI_RESID = 1, EPI_GELU = 2, EPI_EMBED = 3 };
 
 struct GemmParams {
   const void* a; int64_t lda;      // A rows (bf16 or f32)
@@ -80,6 +80,9 @@ struct GemmParams {
   void* out; int64_t ldo; int out_f32;
   // EPI_GELU: hid[r, c] = gelu(result)
   void* hid; int64_t ldh;
+  // EPI_EMBED: A row m is patch i = m % emb_np of frame f = m / emb_np;
+  // x[f * emb_pd + kEmbedSpecial + i, c] = result + pos[1 + i, c] (pos [.., N], bias type)
+  const void* pos; int emb_np, emb_pd;
 };
 
 hipError_t launch_gemm_bf16(const GemmParams& p, Epi epi, hipStream_t s);
@@ -89,6 +92,24 @@ hipError_t launch_gemm_f32(const GemmParams& p, Epi epi, hipStream_t s);
 hipError_t launch_layernorm(const float* x, int64_t ldx, const void* g, const void* b, float eps, void* h,
                             int64_t ldh, int rows, int C, bool bf16_io, hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
+
+// ---- patch-embedding front end (embed.hip)
+constexpr int kEmbedPatch = 14;                          // patch side in pixels
+constexpr int kEmbedSpecial = 5;                         // class / camera token + 4 registers per frame
+constexpr int kEmbedK = 3 * kEmbedPatch * kEmbedPatch;   // 588 values per patch
+constexpr int kEmbedKp = 640;                            // kEmbedK padded to the GEMM's k-step (64)
+constexpr int kEmbedMaxChunk = 2048;                     // frames per front-end chunk (bits of FirstMask)
+struct FirstMask {
+  uint32_t w[kEmbedMaxChunk / 32];  // bit f: chunk frame f is the first frame of a scene
+};
+hipError_t launch_pad_cols(const void* w, void* wp, int rows, int K, int Kp, bool bf16_io, hipStream_t s);
+hipError_t launch_patchify(const float* img, int height, int width, int64_t f0, int n_frames, void* a, int Kp,
+                           bool bf16_io, hipStream_t s);
+hipError_t launch_embed_special(const void* pos, const void* cls, const void* reg, float* x, int n_frames, int Pd,
+                                int C, bool bf16_io, hipStream_t s);
+hipError_t launch_embed_finish(const float* x, int Pd, const void* g, const void* b, float eps, const void* cam,
+                               const void* agg_reg, float* out, int64_t f0, int n_frames, const FirstMask& first,
+                               int C, bool bf16_io, hipStream_t s);
 hipError_t launch_fill_hash_bf16(bf16* x, int64_t n, uint64_t seed, float scale, hipStream_t s);
 
 }  // namespace vggtx

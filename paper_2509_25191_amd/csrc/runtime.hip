@@ -660,6 +660,131 @@ vggtx_status attn_entry(vggtx_handle h, int cls, const void* q, const void* k, c
   return run_attention(h, cls, io, s, H, prec, (hipStream_t)stream);
 }
 
+// -------------------------------------------------------------- front end
+// Shape of one front-end chunk and the workspace it needs: the block
+// workspace for fc frames of Pd tokens, then the patch matrix [fc * n_patch,
+// kEmbedKp] and the zero-padded patch weight [C, kEmbedKp].
+struct EmbedPlan {
+  int n_patch = 0, Pd = 0;
+  int64_t fc = 0;  // frames per chunk
+  WsShape sh;
+  Ws ws;
+  void* a = nullptr;
+  void* wp = nullptr;
+  size_t total = 0;
+};
+
+EmbedPlan embed_plan(const vggtx_config& c, int64_t total_frames, int height, int width, vggtx_prec prec, char* base) {
+  EmbedPlan e;
+  e.n_patch = (height / kEmbedPatch) * (width / kEmbedPatch);
+  e.Pd = kEmbedSpecial + e.n_patch;
+  e.fc = std::max<int64_t>(1, std::min<int64_t>({total_frames, (int64_t)c.frame_chunk, (int64_t)kEmbedMaxChunk}));
+  e.sh.n_tokens = e.fc * e.Pd;
+  e.sh.npad = e.fc * round_up(e.Pd, kKeyPad);
+  e.sh.nblk = e.fc * cdiv(e.Pd, kQuantRows);
+  e.sh.chunk_rows = e.fc * e.Pd;
+  e.ws = carve(c, e.sh, prec, base);
+  const size_t el = prec == VGGTX_F32 ? 4 : 2;
+  size_t off = (size_t)round_up((int64_t)e.ws.total, 256);
+  e.a = base ? (void*)(base + off) : nullptr;
+  off += (size_t)round_up(e.fc * e.n_patch * kEmbedKp * (int64_t)el, 256);
+  e.wp = base ? (void*)(base + off) : nullptr;
+  off += (size_t)round_up((int64_t)c.dim * kEmbedKp * (int64_t)el, 256);
+  e.total = off;
+  return e;
+}
+
+vggtx_status check_embed_w(const vggtx_embed_w* w) {
+  if (!w) return fail(VGGTX_E_INVALID, "front-end weights are null");
+  const void* ptrs[9] = {w->w_patch, w->b_patch, w->pos, w->cls, w->reg, w->norm_g, w->norm_b, w->cam, w->agg_reg};
+  static const char* names[9] = {"w_patch", "b_patch", "pos", "cls", "reg", "norm_g", "norm_b", "cam", "agg_reg"};
+  for (int i = 0; i < 9; ++i) {
+    if (!ptrs[i]) return fail(VGGTX_E_INVALID, "front end: %s is null", names[i]);
+    if ((uintptr_t)ptrs[i] % 16) return fail(VGGTX_E_INVALID, "front end: %s not 16-byte aligned", names[i]);
+  }
+  if (w->depth < 0) return fail(VGGTX_E_INVALID, "front end: depth %d", w->depth);
+  if (w->depth > 0 && !w->blocks) return fail(VGGTX_E_INVALID, "front end: blocks are null");
+  for (int l = 0; l < w->depth; ++l) VGGTX_TRY(check_block_w(w->blocks[l], "front-end", l));
+  return VGGTX_OK;
+}
+
+vggtx_status check_image_shape(int height, int width) {
+  if (height <= 0 || width <= 0 || height % kEmbedPatch || width % kEmbedPatch)
+    return fail(VGGTX_E_INVALID, "image %d x %d: sides must be positive multiples of %d", height, width, kEmbedPatch);
+  return VGGTX_OK;
+}
+
+vggtx_status embed_impl(vggtx_handle h, const float* images, int height, int width, const int32_t* frame_offsets,
+                        int n_scenes, const vggtx_embed_w* w, float* tokens, vggtx_prec prec, void* ws,
+                        size_t ws_bytes, void* stream) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  VGGTX_TRY(check_prec(prec));
+  VGGTX_TRY(check_offsets(frame_offsets, n_scenes, "frame"));
+  VGGTX_TRY(check_image_shape(height, width));
+  VGGTX_TRY(check_embed_w(w));
+  const vggtx_config& c = h->cfg;
+  const vggtx_prec pr = prec == VGGTX_FP8_E4M3 ? VGGTX_BF16 : prec;
+  const int64_t S = frame_offsets[n_scenes];
+  const EmbedPlan need = embed_plan(c, S, height, width, pr, nullptr);
+  if (S * need.Pd > kMaxTokens) return fail(VGGTX_E_UNSUPPORTED, "%lld tokens exceed the supported %lld",
+                                             (long long)(S * need.Pd), (long long)kMaxTokens);
+  if (S == 0) return VGGTX_OK;
+  if (!images || !tokens) return fail(VGGTX_E_INVALID, "images %p / tokens %p is null", (const void*)images, (void*)tokens);
+  if ((uintptr_t)images % 16 || (uintptr_t)tokens % 16) return fail(VGGTX_E_INVALID, "images / tokens must be 16-byte aligned");
+  if (!ws || ws_bytes < need.total)
+    return fail(VGGTX_E_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need.total);
+  if ((uintptr_t)ws % 256) return fail(VGGTX_E_INVALID, "workspace must be 256-byte aligned");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+
+  const EmbedPlan e = embed_plan(c, S, height, width, pr, (char*)ws);
+  const bool lp = lowp(pr);
+  const int C = c.dim;
+  hipStream_t st = (hipStream_t)stream;
+  {
+    Span sp(h, VGGTX_K_OTHER, 0.0, st);
+    VGGTX_HIP(launch_pad_cols(w->w_patch, e.wp, C, kEmbedK, kEmbedKp, lp, st));
+  }
+  std::vector<char> first((size_t)S, 0);
+  for (int i = 0; i < n_scenes; ++i)
+    if (frame_offsets[i + 1] > frame_offsets[i]) first[frame_offsets[i]] = 1;
+  for (int64_t f0 = 0; f0 < S; f0 += e.fc) {
+    const int nf = (int)std::min<int64_t>(e.fc, S - f0);
+    BlockRun br;
+    br.ctx = h;
+    br.prec = pr;
+    br.ws = e.ws;
+    br.N = (int64_t)nf * e.Pd;
+    br.stream = st;
+    {
+      Span sp(h, VGGTX_K_OTHER, 0.0, st);
+      VGGTX_HIP(launch_patchify(images, height, width, f0, nf, e.a, kEmbedKp, lp, st));
+      VGGTX_HIP(launch_embed_special(w->pos, w->cls, w->reg, e.ws.x, nf, e.Pd, C, lp, st));
+    }
+    GemmParams g;
+    memset(&g, 0, sizeof(g));
+    g.a = e.a; g.lda = kEmbedKp;
+    g.w = e.wp; g.bias = w->b_patch;
+    g.M = nf * e.n_patch; g.N = C; g.K = kEmbedKp;
+    g.x = e.ws.x; g.ldx = C;
+    g.pos = w->pos; g.emb_np = e.n_patch; g.emb_pd = e.Pd;
+    {
+      Span sp(h, VGGTX_K_GEMM, 2.0 * g.M * C * kEmbedK, st);
+      VGGTX_HIP((lp ? launch_gemm_bf16 : launch_gemm_f32)(g, EPI_EMBED, st));
+    }
+    for (int l = 0; l < w->depth; ++l)
+      VGGTX_TRY(block_frames(br, w->blocks[l], nf, e.Pd, nf, e.sh.npad, e.sh.nblk, nullptr, 0, false));
+    FirstMask fm;
+    memset(&fm, 0, sizeof(fm));
+    for (int f = 0; f < nf; ++f)
+      if (first[f0 + f]) fm.w[f >> 5] |= 1u << (f & 31);
+    Span sp(h, VGGTX_K_OTHER, 0.0, st);
+    VGGTX_HIP(launch_embed_finish(e.ws.x, e.Pd, w->norm_g, w->norm_b, c.ln_eps, w->cam, w->agg_reg, tokens, f0, nf, fm,
+                                  C, lp, st));
+  }
+  return VGGTX_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C-ABI
@@ -760,6 +885,23 @@ vggtx_status vggtx_block(vggtx_handle h, const float* x_in, float* x_out, const 
   const Seqs s = seqs_from_offsets(seq_offsets, n_seq, 1);
   const int64_t chunk_rows = std::max<int64_t>(1, std::min<int64_t>(N, (int64_t)c.frame_chunk * std::max(1, lmax)));
   return block_global(br, *w, s, chunk_rows, prec == VGGTX_FP8_E4M3, sh.npad, sh.nblk, nullptr, 0, false);
+}
+
+vggtx_status vggtx_embed_workspace_size(vggtx_handle h, int total_frames, int height, int width, vggtx_prec prec,
+                                        size_t* bytes) {
+  if (!h || !bytes) return fail(VGGTX_E_INVALID, "handle / bytes is null");
+  VGGTX_TRY(check_prec(prec));
+  VGGTX_TRY(check_image_shape(height, width));
+  if (total_frames < 0) return fail(VGGTX_E_INVALID, "frames %d", total_frames);
+  const vggtx_prec pr = prec == VGGTX_FP8_E4M3 ? VGGTX_BF16 : prec;
+  *bytes = embed_plan(h->cfg, total_frames, height, width, pr, nullptr).total;
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_embed(vggtx_handle h, const float* images, int height, int width, const int32_t* frame_offsets,
+                         int n_scenes, const vggtx_embed_w* w, float* tokens, vggtx_prec prec, void* ws,
+                         size_t ws_bytes, void* stream) {
+  return embed_impl(h, images, height, width, frame_offsets, n_scenes, w, tokens, prec, ws, ws_bytes, stream);
 }
 
 vggtx_status vggtx_attn_workspace_size(vggtx_handle h, const int32_t* seq_offsets, int n_seq, int H, int D,

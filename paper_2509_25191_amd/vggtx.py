@@ -17,7 +17,7 @@ __all__ = [
     "Config", "BlockW", "PairW", "Layout", "Handle", "create", "destroy", "workspace_size",
     "aggregate", "aggregate_varlen", "block", "attn_workspace_size", "attn_frame", "attn_global",
     "quantize_fp8", "status_str", "last_error", "BLOCK_FIELDS", "timing_enable", "timing_read", "timing_poll",
-    "autotune_workspace_size", "autotune",
+    "autotune_workspace_size", "autotune", "EmbedW", "EMBED_FIELDS", "embed_workspace_size", "embed",
     "K_ATTN_GLOBAL", "K_ATTN_FRAME", "K_GEMM", "K_OTHER",
 ]
 
@@ -54,6 +54,16 @@ class PairW(ctypes.Structure):
     _fields_ = [("frame", BlockW), ("global_", BlockW)]
 
 
+EMBED_FIELDS = ("w_patch", "b_patch", "pos", "cls", "reg", "norm_g", "norm_b", "cam", "agg_reg")
+
+
+class EmbedW(ctypes.Structure):
+    _fields_ = [("w_patch", ctypes.c_void_p), ("b_patch", ctypes.c_void_p), ("pos", ctypes.c_void_p),
+                ("cls", ctypes.c_void_p), ("reg", ctypes.c_void_p), ("blocks", ctypes.POINTER(BlockW)),
+                ("depth", ctypes.c_int), ("norm_g", ctypes.c_void_p), ("norm_b", ctypes.c_void_p),
+                ("cam", ctypes.c_void_p), ("agg_reg", ctypes.c_void_p)]
+
+
 class Layout(ctypes.Structure):
     _fields_ = [("token_stride", ctypes.c_int64), ("head_stride", ctypes.c_int64)]
 
@@ -87,6 +97,8 @@ def load():
         "vggtx_quantize_fp8": [vp, vp, Layout, P_i32, i32, i32, i32, vp, vp, vp],
         "vggtx_autotune_workspace_size": [vp, i32, ctypes.POINTER(sz)],
         "vggtx_autotune": [vp, i32, i32, vp, sz, vp, ctypes.POINTER(i32)],
+        "vggtx_embed_workspace_size": [vp, i32, i32, i32, i32, ctypes.POINTER(sz)],
+        "vggtx_embed": [vp, vp, i32, i32, P_i32, i32, ctypes.POINTER(EmbedW), vp, i32, vp, sz, vp],
         "vggtx_timing_enable": [vp, i32],
         "vggtx_timing_read": [vp, ctypes.POINTER(Timing), ctypes.POINTER(ctypes.c_int64)],
         "vggtx_timing_poll": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -268,6 +280,36 @@ def autotune(h, prec: int, n_tokens: int = 32768, ws: Optional[torch.Tensor] = N
     _check(load().vggtx_autotune(h, int(prec), int(n_tokens), _ptr(ws), ws.numel(), _stream(stream),
                                  ctypes.byref(chosen)))
     return chosen.value
+
+
+def embed_workspace_size(h, total_frames: int, height: int, width: int, prec: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load().vggtx_embed_workspace_size(h, int(total_frames), int(height), int(width), int(prec),
+                                             ctypes.byref(n)))
+    return n.value
+
+
+def embed(h, images: torch.Tensor, params: Dict[str, object], prec: int, frame_offsets: Optional[Sequence[int]] = None,
+          out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Front end: images [S, 3, height, width] float32 -> aggregator tokens [S, 5 + n_patches, C] float32.
+    params: the EMBED_FIELDS tensors plus "blocks" (a list of block parameter dicts)."""
+    S, _, height, width = images.shape
+    C = params["norm_g"].shape[0]
+    P = 5 + (height // 14) * (width // 14)
+    if frame_offsets is None:
+        frame_offsets = [0, S]
+    if out is None:
+        out = torch.empty((S, P, C), dtype=torch.float32, device=images.device)
+    if ws is None:
+        ws = _alloc_ws(embed_workspace_size(h, S, height, width, prec), images.device)
+    blocks = params["blocks"]
+    barr = (BlockW * max(1, len(blocks)))(*[block_w(b) for b in blocks])
+    ew = EmbedW(*[ctypes.c_void_p(params[n].data_ptr()) for n in EMBED_FIELDS[:5]],
+                ctypes.cast(barr, ctypes.POINTER(BlockW)), len(blocks),
+                *[ctypes.c_void_p(params[n].data_ptr()) for n in EMBED_FIELDS[5:]])
+    _check(load().vggtx_embed(h, _ptr(images), height, width, _i32_array(frame_offsets), len(frame_offsets) - 1,
+                              ctypes.byref(ew), _ptr(out), int(prec), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
 
 
 def timing_enable(h, enable: bool = True) -> None:

@@ -69,3 +69,12 @@ def test_no_device_reports_nodevice():
     h = ctypes.c_void_p()
     ok = vg.Config(256, 4, 64, 1024, 1e-6, 128)
     assert lib.vggtx_create(ctypes.byref(h), 0, ctypes.byref(ok)) == 5
+
+
+def test_front_end_rejects_bad_calls_without_device():
+    lib = vg.load()
+    n = ctypes.c_size_t()
+    assert lib.vggtx_embed_workspace_size(None, 4, 518, 518, vg.BF16, ctypes.byref(n)) == 1
+    off = (ctypes.c_int32 * 2)(0, 4)
+    assert lib.vggtx_embed(None, None, 518, 518, off, 1, None, None, vg.BF16, None, 0, None) == 1
+    assert "null" in vg.last_error()
