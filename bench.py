@@ -156,6 +156,97 @@ def cpu_baseline(S, P, C=1024, H=16, F=4096, depth=24):
     return {"value": S / total, "unit": "frames/s", "cores": int(cores), "kind": "oracle", "sample": sample}
 
 
+def make_embed_weights(model, gen, dtype, dev, n_patch, depth):
+    """Front-end parameters (shapes of the C ABI's vggtx_embed_w), N(0, 0.02), norm_g = 1 + N(0, 0.02)."""
+    C = model.dim
+
+    def draw(shape, one=False):
+        t = torch.empty(shape, device=dev, dtype=torch.float32).normal_(0.0, 0.02, generator=gen)
+        return (t + 1.0 if one else t).to(dtype)
+
+    w = {"w_patch": draw((C, 588)), "b_patch": draw((C,)), "pos": draw((1 + n_patch, C)), "cls": draw((C,)),
+         "reg": draw((4, C))}
+    w["blocks"] = [l["frame"] for l in make_weights(synth.ModelConfig(depth=depth), gen, dtype, dev)]
+    w.update({"norm_g": draw((C,), one=True), "norm_b": draw((C,)), "cam": draw((2, C)), "agg_reg": draw((2, 4, C))})
+    return w
+
+
+def embed_cpu_baseline(w_np, img_np, H):
+    """FP64 oracle front end on one frame (the front end is per frame), scaled to frames/s."""
+    import threadpoolctl
+
+    import oracle
+    t0 = time.perf_counter()
+    oracle.embed(img_np, w_np, H, 1e-6, frames=[0])
+    t = time.perf_counter() - t0
+    info = threadpoolctl.threadpool_info()
+    cores = max([i.get("num_threads", 1) for i in info] + [1])
+    return {"value": 1.0 / t, "unit": "frames/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"oracle front end on 1 frame of 518x518 with 24 blocks ({t:.2f}s); frames are independent"}
+
+
+def bench_embed(args, dev):
+    """Patch-embedding front end (per-frame ViT-L/14 at 518 x 518, 24 blocks, BF16)."""
+    S, Hi, Wi, depth = args.frames, 518, 518, 24
+    model = synth.ModelConfig()
+    n_patch = (Hi // 14) * (Wi // 14)
+    P = 5 + n_patch
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(args.seed)
+    log(f"front end: generating S={S} images {Hi}x{Wi}, depth {depth}")
+    images = torch.empty((S, 3, Hi, Wi), device=dev, dtype=torch.float32).normal_(0, 1, generator=gen)
+    w = make_embed_weights(model, gen, torch.bfloat16, dev, n_patch, depth)
+    h = vg.Handle(0, dim=model.dim, heads=model.heads, head_dim=model.head_dim, mlp_hidden=model.mlp_hidden,
+                  ln_eps=model.ln_eps, frame_chunk=model.frame_chunk)
+    ws = torch.empty(vg.embed_workspace_size(h.h, S, Hi, Wi, vg.BF16), dtype=torch.uint8, device=dev)
+    out = torch.empty((S, P, model.dim), device=dev, dtype=torch.float32)
+    vg.embed(h.h, images[:1], w, vg.BF16, out=out[:1], ws=ws)  # loads the kernels (not a step)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats(dev)
+    for i in range(args.warmup):
+        vg.embed(h.h, images, w, vg.BF16, out=out, ws=ws)
+        torch.cuda.synchronize()
+        log(f"warmup step {i} done")
+    vg.timing_enable(h.h, True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(args.steps):
+        vg.embed(h.h, images, w, vg.BF16, out=out, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    tm = vg.timing_read(h.h)
+    vg.timing_enable(h.h, False)
+    log(f"front end: {args.steps} step(s) in {sec:.3f}s")
+    gm, fa = tm["gemm"], tm["attn_frame"]
+    g_tf = gm["flops"] / (gm["ms"] * 1e-3) / 1e12 if gm["ms"] > 0 else None
+    f_tf = fa["flops"] / (fa["ms"] * 1e-3) / 1e12 if fa["ms"] > 0 else None
+    res = {
+        "metric": "front-end frames/s (per-frame patch embedding + 24 ViT-L/14 blocks at 518x518)",
+        "value": S * args.steps / sec, "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic (images N(0,1), weights N(0,0.02), seeded, device-generated)",
+        "config": {"workload": f"vitl14_frontend_S{S}_{Hi}x{Wi}", "frames": S, "image": [Hi, Wi],
+                   "tokens_per_frame": P, "dim": model.dim, "heads": model.heads, "mlp_hidden": model.mlp_hidden,
+                   "depth": depth, "frame_chunk": model.frame_chunk},
+        "gemm_tflops": g_tf, "frame_attn_tflops": f_tf,
+        "kernel_time_ms": {k: v["ms"] for k, v in tm.items() if isinstance(v, dict)},
+        "peak_hbm_gb": torch.cuda.max_memory_allocated(dev) / 1e9,
+        "roofline": {"kernel": "gemm_bf16_kernel (projections, MLP, patch embedding)", "bound": "mfma",
+                     "achieved": g_tf, "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+                     "frac": g_tf / PEAK_TFLOPS["bf16"] if g_tf else None, "traffic": None,
+                     "flops_per_launch": gm["flops"] / max(1, gm["launches"]),
+                     "avg_launch_ms": gm["ms"] / max(1, gm["launches"]), "launches": gm["launches"]},
+    }
+    h.close()
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle front end on one frame")
+        w_np = {k: (v.float().cpu().numpy() if k != "blocks" else [{kk: vv.float().cpu().numpy() for kk, vv in b.items()}
+                                                                 for b in v]) for k, v in w.items()}
+        res["cpu_baseline"] = embed_cpu_baseline(w_np, images[:1].cpu().numpy(), model.heads)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +259,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 2 GiB device to device (calibrates HBM byte counters)")
+    ap.add_argument("--stage", choices=["aggregator", "embed"], default="aggregator",
+                    help="aggregator (default): the aggregator forward; embed: the patch-embedding front end")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
@@ -176,6 +269,9 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.stage == "embed":
+        bench_embed(args, dev)
+        return
     S, P = args.frames, P_TOKENS
     model = synth.ModelConfig()
     prec = PREC[args.prec]
