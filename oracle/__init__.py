@@ -1,4 +1,5 @@
-"""FP64 CPU oracle of the VGGT-X memory-efficient aggregator (arXiv 2509.25191, Sec. 3.2).
+"""FP64 CPU oracle of the VGGT-X memory-efficient aggregator (arXiv 2509.25191, Sec. 3.2),
+its patch-embedding front end and the camera global alignment (Sec. 3.3).
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the GPU library imports, links or calls
 this package; only the test-suite, the smoke check and the benchmark's CPU
@@ -25,6 +26,10 @@ Parity status by function (what pins each one is listed in tests/test_oracle.py)
   patchify, frame_tokens, embed (the patch-embedding front end): pinned
   (patch embedding against a float64 Conv2d and a brute-force loop, depth-0
   closed form, frame permutation and scene-first token rules).
+  ga (global alignment): pinned (residual against rectified-stereo and
+  projected-ray constructions, gradient against torch autograd, Adam against
+  torch.optim.Adam, histogram weights against a hand-worked example, the
+  median rule against numpy.median, pair selection against a camera ring).
   Agreement of the whole network with a trained VGGT: parity unpinned (no
   trained weights or worked numeric example exist for this path).
 """
@@ -36,3 +41,4 @@ from .aggregator import (  # noqa: F401
 from .fp8 import (e4m3_decode, e4m3_encode, quantize_rows, attention_fp8_emulated, block_exponent,  # noqa: F401
                   logit_factor, E4M3_MAX)
 from .embed import patchify, frame_tokens, embed  # noqa: F401
+from . import ga  # noqa: F401

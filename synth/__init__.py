@@ -20,6 +20,7 @@ paper evaluates on, which are not available; their sequence lengths of up to
 from __future__ import annotations
 
 import dataclasses
+import math
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
@@ -222,3 +223,77 @@ def gen_embed(rng: np.random.Generator, model: ModelConfig, height: int, width: 
     w["cam"] = draw((2, C))
     w["agg_reg"] = draw((2, EMBED_SPECIAL - 1, C))
     return w
+
+
+# --------------------------------------------------------------------------
+# global alignment: cameras and correspondences
+# --------------------------------------------------------------------------
+
+def _look_at_origin(C: np.ndarray) -> np.ndarray:
+    """World-to-camera rotation whose optical axis (third row) points from C to the origin."""
+    z = -C / np.linalg.norm(C)
+    x = np.cross(np.array([0.0, 1.0, 0.0]), z)
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    return np.stack([x, y, z])
+
+
+def _small_rotation(v: np.ndarray) -> np.ndarray:
+    """Rotation by the axis-angle vector v (Rodrigues)."""
+    a = float(np.linalg.norm(v))
+    if a == 0.0:
+        return np.eye(3)
+    k = v / a
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + math.sin(a) * K + (1 - math.cos(a)) * (K @ K)
+
+
+def gen_ga_cameras(rng: np.random.Generator, n_cams: int, arc_deg: float = 360.0, radius: float = 4.0,
+                   focal: float = 500.0, size: int = 518, rot_noise_deg: float = 1.0, trans_noise: float = 0.05,
+                   focal_noise: float = 0.02):
+    """True cameras on a horizontal arc of `arc_deg` degrees (radius `radius`,
+    small random height), all looking at the origin, focal `focal`, principal
+    point at the image centre; and the predicted (initial) cameras: the true
+    ones with a random rotation of std rot_noise_deg per axis, centre noise of
+    std trans_noise and relative focal noise of std focal_noise.  Returns two
+    dicts with R [N,3,3], t [N,3], f [N], c [N,2] (float64)."""
+    yaw = np.radians(np.linspace(0.0, arc_deg, n_cams, endpoint=arc_deg < 360.0))
+    height = rng.normal(0.0, 0.3, n_cams)
+    true = {"R": np.empty((n_cams, 3, 3)), "t": np.empty((n_cams, 3)), "f": np.full(n_cams, float(focal)),
+            "c": np.full((n_cams, 2), size / 2.0)}
+    init = {"R": np.empty((n_cams, 3, 3)), "t": np.empty((n_cams, 3)), "f": np.empty(n_cams),
+            "c": np.full((n_cams, 2), size / 2.0)}
+    for n in range(n_cams):
+        C = np.array([radius * math.sin(yaw[n]), height[n], -radius * math.cos(yaw[n])])
+        R = _look_at_origin(C)
+        true["R"][n], true["t"][n] = R, -R @ C
+        Ri = _small_rotation(rng.normal(0.0, math.radians(rot_noise_deg), 3)) @ R
+        Ci = C + rng.normal(0.0, trans_noise, 3)
+        init["R"][n], init["t"][n] = Ri, -Ri @ Ci
+        init["f"][n] = focal * (1.0 + rng.normal(0.0, focal_noise))
+    return true, init
+
+
+def gen_ga_corr(rng: np.random.Generator, cams: Dict[str, np.ndarray], pairs: np.ndarray, per_pair,
+                noise_px: float = 0.5, outlier_frac: float = 0.2, size: int = 518, spread: float = 0.7):
+    """Correspondences of the pairs: scene points N(0, spread^2) per axis
+    projected into both true cameras, pixel noise of std noise_px, and a
+    fraction outlier_frac whose second point is replaced by a uniform random
+    pixel.  per_pair: int or a sequence with one count per pair.  Returns
+    (corr float32 [K, 4] = (u, v, u', v'), offsets int64 [n_pairs + 1])."""
+    counts = np.full(len(pairs), per_pair) if np.isscalar(per_pair) else np.asarray(per_pair)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    corr = np.empty((offsets[-1], 4), np.float32)
+    R, t, f, c = cams["R"], cams["t"], cams["f"], cams["c"]
+    for m, (i, j) in enumerate(pairs):
+        n = int(counts[m])
+        X = rng.normal(0.0, spread, (n, 3))
+        uv = []
+        for cam in (i, j):
+            Xc = X @ R[cam].T + t[cam]
+            uv.append(np.stack([f[cam] * Xc[:, 0] / Xc[:, 2] + c[cam, 0], f[cam] * Xc[:, 1] / Xc[:, 2] + c[cam, 1]], 1))
+        a = np.concatenate(uv, 1) + rng.normal(0.0, noise_px, (n, 4))
+        bad = rng.random(n) < outlier_frac
+        a[bad, 2:] = rng.uniform(0.0, size, (int(bad.sum()), 2))
+        corr[offsets[m]:offsets[m + 1]] = a
+    return corr, offsets
