@@ -250,6 +250,71 @@ vggtx_status vggtx_embed(vggtx_handle h, const float* images, int height, int wi
                          const int32_t* frame_offsets, int n_scenes, const vggtx_embed_w* w,
                          float* tokens, vggtx_prec prec, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- global alignment
+ * Camera global alignment (Sec. 3.3): refine every camera by minimising the
+ * weighted mean epipolar residual of Eq. (epi) over the correspondences of
+ * the image pairs, with the weights of Eq. (weight) and the learning-rate
+ * rule of Eq. (lr).  The paper leaves the details open; the reading built
+ * here (float64 throughout):
+ *   camera     x_cam = R X + t; pixel = (f x/z + cx, f y/z + cy); the
+ *              principal point is fixed, R, t and f are refined
+ *   residual   e = |x'^T F x| / |(F x)_{0,1}|, the pixel distance of x' from
+ *              the epipolar line of x; F = Kj^-T [t_ij]x R_ij Ki^-1 with
+ *              R_ij = Rj Ri^T, t_ij = tj - R_ij ti for the pair (i, j)
+ *   weights    from the residuals of the initial cameras: histogram of bins
+ *              of 0.1 px over [0, 20) plus an overflow bin of density 0;
+ *              f(b) = count_b / (K * 0.1), w = (f / Avg_k f(e_k))^alpha
+ *              (all weights 1 when no residual is below 20 px)
+ *   rate       the bin of the ceil(K/2)-th smallest initial residual picks
+ *              lr[0] (median < bounds[0]), lr[1] (< bounds[1]) or lr[2]
+ *   optimiser  Adam on (unnormalised quaternion, t, log f) per camera,
+ *              `iterations` steps, weights and rate fixed
+ * Degenerate pairs (coincident camera centres, F = 0) are not supported. */
+typedef struct {
+  int iterations;     /* 300 */
+  double lr[3];       /* 5e-4, 1e-3, 1e-2 */
+  double bounds[2];   /* 2.5, 7.5 pixels; multiples of 0.1 in [0, 20] */
+  double alpha;       /* 0.5 */
+  double beta1, beta2, eps;  /* Adam: 0.9, 0.999, 1e-8 */
+} vggtx_ga_config;
+
+/* The paper's settings (Sec. 4.1) and Adam's usual constants. */
+void vggtx_ga_config_default(vggtx_ga_config* cfg);
+
+/* Candidate pairs (Sec. 3.3: views that differ by less than max_angle_deg,
+ * 30 in Sec. 4.1), the angle being that between the optical axes (third rows
+ * of R).  Host-only: R is host float64 [n_cams, 3, 3]; pairs receives (i, j),
+ * i < j, in row-major order of (i, j) when it is not null.  *n_pairs receives
+ * the number of pairs; VGGTX_E_INVALID when pairs is not null and more than
+ * max_pairs exist (nothing is written then). */
+vggtx_status vggtx_ga_select_pairs(const double* R, int n_cams, double max_angle_deg, int32_t* pairs, int max_pairs,
+                                   int* n_pairs);
+
+/* Workspace bytes vggtx_ga_align needs. */
+vggtx_status vggtx_ga_workspace_size(vggtx_handle h, int n_cams, int n_pairs, int64_t n_corr, size_t* bytes);
+
+/* Global alignment.
+ *   R0, t0, f0, pp  device float64 [n_cams,3,3], [n_cams,3], [n_cams], [n_cams,2]: the
+ *                   predicted cameras (f0 > 0) and their principal points
+ *   pairs           host int32 [n_pairs, 2], camera indices i != j
+ *   corr_offsets    host int64 [n_pairs + 1], 0 = first, non-decreasing: the
+ *                   correspondences of pair m are rows corr_offsets[m] ..
+ *                   corr_offsets[m+1]-1 of corr
+ *   corr            device float32 [n_corr, 4] = (u, v, u', v'): pixel x in
+ *                   camera i and x' in camera j; 16-byte aligned
+ *   R_out, t_out, f_out  device float64, the refined cameras (same shapes)
+ *   weights_out     device float32 [n_corr] or null: w of every correspondence
+ *   loss_out        device float64 [iterations + 1] or null: the loss before
+ *                   each step and after the last one
+ * The host tables are copied into the workspace and `stream` is synchronised
+ * once before the kernels are enqueued, so the host arrays may be released
+ * when the call returns; the alignment itself runs asynchronously. */
+vggtx_status vggtx_ga_align(vggtx_handle h, const vggtx_ga_config* cfg, int n_cams, const double* R0,
+                            const double* t0, const double* f0, const double* pp, const int32_t* pairs,
+                            int n_pairs, const int64_t* corr_offsets, const float* corr, double* R_out,
+                            double* t_out, double* f_out, float* weights_out, double* loss_out, void* ws,
+                            size_t ws_bytes, void* stream);
+
 /* Kernel timing (tracing).  While enabled, every kernel launch of the classes
  * below is bracketed by a pair of HIP events recorded on its launch stream, and
  * vggtx_timing_read() waits for those events and returns, per class, the summed

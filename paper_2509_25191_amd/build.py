@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libvggtx.so")
 BUILD_DIR = os.path.join(os.path.dirname(PKG), "_build")
-SOURCES = ["attention.hip", "gemm.hip", "elementwise.hip", "embed.hip", "runtime.hip"]
+SOURCES = ["attention.hip", "gemm.hip", "elementwise.hip", "embed.hip", "ga.hip", "runtime.hip"]
 ARCH = "gfx950"
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

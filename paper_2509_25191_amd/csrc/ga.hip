@@ -1,0 +1,434 @@
+// Camera global alignment (arXiv 2509.25191, Sec. 3.3, Eqs. epi / weight / lr):
+// refine every camera (rotation, translation, focal length) by Adam on the
+// weighted mean epipolar distance of the pairwise correspondences, with the
+// weights taken from a histogram of the initial residuals and the learning
+// rate from their median.  All arithmetic is float64: the work is bound by
+// streaming the correspondences (16 + 1 bytes each per iteration), and the
+// vector units run float64 at half the float32 rate.
+//
+// Per camera n the parameters are p[n] = (q0..q3, t0..t2, phi): R = R(q/|q|),
+// t, f = f0 exp(phi).  A pair (i, j) has R_ij = R_j R_i^T, t_ij = t_j - R_ij t_i
+// and F = K_j^-T [t_ij]_x R_ij K_i^-1; a correspondence (x, x') has the
+// residual e = |x'^T F x| / |(F x)_{0,1}|, the pixel distance of x' from the
+// epipolar line of x.
+//
+// Kernels (one workgroup per pair streams that pair's correspondences):
+//   ga_init_kernel   parameters from the initial cameras, Adam state zeroed
+//   ga_pair_kernel   MODE_BINS: residual histogram bin of every correspondence
+//                    (initial cameras) and the global bin counts;
+//                    MODE_GRAD: per pair sum_k w_k e_k and the gradient of it
+//                    with respect to the 16 parameters of the two cameras;
+//                    MODE_LOSS: sum_k w_k e_k only
+//   ga_table_kernel  weight per bin, total weight, learning rate (median bin)
+//   ga_adam_kernel   per camera: sum of its pairs' gradients / W, Adam step
+//   ga_loss_kernel   sum of the pair losses / W into the loss history
+//   ga_out_kernel    R, t, f of the parameters; optional per-correspondence weights
+#include <algorithm>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace vggtx {
+
+namespace {
+
+struct M3 {
+  double a[3][3];
+};
+
+__device__ __forceinline__ M3 mul(const M3& x, const M3& y) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.a[i][j] = x.a[i][0] * y.a[0][j] + x.a[i][1] * y.a[1][j] + x.a[i][2] * y.a[2][j];
+  return r;
+}
+__device__ __forceinline__ M3 tr(const M3& x) {
+  M3 r;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.a[i][j] = x.a[j][i];
+  return r;
+}
+__device__ __forceinline__ M3 skew3(const double t[3]) {
+  M3 r = {{{0.0, -t[2], t[1]}, {t[2], 0.0, -t[0]}, {-t[1], t[0], 0.0}}};
+  return r;
+}
+// K^-1 for focal f and principal point (cx, cy)
+__device__ __forceinline__ M3 kinv(double f, double cx, double cy) {
+  M3 r = {{{1.0 / f, 0.0, -cx / f}, {0.0, 1.0 / f, -cy / f}, {0.0, 0.0, 1.0}}};
+  return r;
+}
+// numerator matrix N(q) with R(q / |q|) = N(q) / |q|^2
+__device__ __forceinline__ M3 quat_num(const double q[4]) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  M3 r = {{{w * w + x * x - y * y - z * z, 2 * (x * y - w * z), 2 * (x * z + w * y)},
+           {2 * (x * y + w * z), w * w - x * x + y * y - z * z, 2 * (y * z - w * x)},
+           {2 * (x * z - w * y), 2 * (y * z + w * x), w * w - x * x - y * y + z * z}}};
+  return r;
+}
+__device__ __forceinline__ M3 quat_rot(const double q[4]) {
+  M3 r = quat_num(q);
+  const double inv = 1.0 / (q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r.a[i][j] *= inv;
+  return r;
+}
+
+// Camera of the pair side: R, t, f, principal point.
+struct Cam {
+  M3 R;
+  double t[3], f, cx, cy;
+};
+__device__ __forceinline__ Cam load_cam(const double* p, const double* f0, const double* pp, int n) {
+  Cam c;
+  const double* q = p + 8 * n;
+  c.R = quat_rot(q);
+  c.t[0] = q[4]; c.t[1] = q[5]; c.t[2] = q[6];
+  c.f = f0[n] * exp(q[7]);
+  c.cx = pp[2 * n]; c.cy = pp[2 * n + 1];
+  return c;
+}
+
+// Fundamental matrix of the pair and the intermediates of its chain rule.
+struct PairGeom {
+  M3 Rij, E, Ki, Kj, F;
+  double tij[3];
+};
+__device__ __forceinline__ PairGeom pair_geom(const Cam& ci, const Cam& cj) {
+  PairGeom g;
+  g.Rij = mul(cj.R, tr(ci.R));
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    g.tij[r] = cj.t[r] - (g.Rij.a[r][0] * ci.t[0] + g.Rij.a[r][1] * ci.t[1] + g.Rij.a[r][2] * ci.t[2]);
+  g.E = mul(skew3(g.tij), g.Rij);
+  g.Ki = kinv(ci.f, ci.cx, ci.cy);
+  g.Kj = kinv(cj.f, cj.cx, cj.cy);
+  g.F = mul(mul(tr(g.Kj), g.E), g.Ki);
+  return g;
+}
+
+// Residual of one correspondence; with GRAD also de/dF = g x^T (g returned).
+__device__ __forceinline__ double residual(const M3& F, const f32x4 c, double g[3], bool grad) {
+  const double x[3] = {(double)c[0], (double)c[1], 1.0};
+  const double xp[3] = {(double)c[2], (double)c[3], 1.0};
+  double l[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) l[r] = F.a[r][0] * x[0] + F.a[r][1] * x[1] + F.a[r][2];
+  const double s = xp[0] * l[0] + xp[1] * l[1] + l[2];
+  const double rn = 1.0 / sqrt(l[0] * l[0] + l[1] * l[1]);
+  const double e = fabs(s) * rn;
+  if (grad) {
+    const double sg = s > 0.0 ? rn : (s < 0.0 ? -rn : 0.0);
+    const double er2 = e * rn * rn;
+    g[0] = sg * xp[0] - er2 * l[0];
+    g[1] = sg * xp[1] - er2 * l[1];
+    g[2] = sg;
+  }
+  return e;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void ga_init_kernel(const double* R0, const double* t0, int n_cams, double* p,
+                                                      double* adam) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= n_cams) return;
+  const double* m = R0 + 9 * n;
+  // quaternion (w >= 0) from the largest of the four diagonal combinations
+  const double tr0 = m[0] + m[4] + m[8];
+  const double cand[4] = {tr0, m[0] - m[4] - m[8], m[4] - m[0] - m[8], m[8] - m[0] - m[4]};
+  int k = 0;
+  for (int i = 1; i < 4; ++i)
+    if (cand[i] > cand[k]) k = i;
+  const double s = sqrt(fmax(cand[k] + 1.0, 0.0)) * 2.0;
+  double q[4];
+  if (k == 0) {
+    q[0] = s / 4; q[1] = (m[7] - m[5]) / s; q[2] = (m[2] - m[6]) / s; q[3] = (m[3] - m[1]) / s;
+  } else if (k == 1) {
+    q[0] = (m[7] - m[5]) / s; q[1] = s / 4; q[2] = (m[1] + m[3]) / s; q[3] = (m[2] + m[6]) / s;
+  } else if (k == 2) {
+    q[0] = (m[2] - m[6]) / s; q[1] = (m[1] + m[3]) / s; q[2] = s / 4; q[3] = (m[5] + m[7]) / s;
+  } else {
+    q[0] = (m[3] - m[1]) / s; q[1] = (m[2] + m[6]) / s; q[2] = (m[5] + m[7]) / s; q[3] = s / 4;
+  }
+  const double sg = q[0] >= 0.0 ? 1.0 : -1.0;
+  double* o = p + 8 * n;
+  for (int i = 0; i < 4; ++i) o[i] = sg * q[i];
+  for (int i = 0; i < 3; ++i) o[4 + i] = t0[3 * n + i];
+  o[7] = 0.0;
+  for (int i = 0; i < 16; ++i) adam[16 * n + i] = 0.0;
+}
+
+// One workgroup (256 threads) per pair.
+template <int MODE>
+__global__ __launch_bounds__(256) void ga_pair_kernel(GaParams a) {
+  __shared__ double red[4];
+  __shared__ uint32_t hist[kGaBins + 1];
+  const int m = blockIdx.x;
+  const int i = a.pairs[2 * m], j = a.pairs[2 * m + 1];
+  const int64_t k0 = a.offsets[m], k1 = a.offsets[m + 1];
+  const Cam ci = load_cam(a.p, a.f0, a.pp, i);
+  const Cam cj = load_cam(a.p, a.f0, a.pp, j);
+  const PairGeom pg = pair_geom(ci, cj);
+  const f32x4* corr = (const f32x4*)a.corr;
+  if (MODE == GA_MODE_BINS) {
+    for (int b = threadIdx.x; b <= kGaBins; b += 256) hist[b] = 0u;
+    __syncthreads();
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+      double g[3];
+      const double e = residual(pg.F, corr[k], g, false);
+      const int b = e < (double)kGaBins / kGaBinsPerPixel ? (int)floor(e * kGaBinsPerPixel) : kGaBins;
+      a.bins[k] = (uint8_t)b;
+      atomicAdd(&hist[b], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b <= kGaBins; b += 256)
+      if (hist[b]) atomicAdd(&a.hist[b], hist[b]);
+    return;
+  }
+  // weighted residual sum and, for MODE_GRAD, sum_k w_k (de_k/dF)
+  double acc[10] = {};
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+    const double w = a.table[a.bins[k]];
+    const f32x4 c = corr[k];
+    double g[3];
+    const double e = residual(pg.F, c, g, MODE == GA_MODE_GRAD);
+    acc[9] += w * e;
+    if (MODE == GA_MODE_GRAD) {
+      const double x0 = (double)c[0], x1 = (double)c[1];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double wg = w * g[r];
+        acc[3 * r] += wg * x0;
+        acc[3 * r + 1] += wg * x1;
+        acc[3 * r + 2] += wg;
+      }
+    }
+  }
+  if (MODE == GA_MODE_LOSS) {
+    const double s = block_sum(acc[9], red);
+    if (threadIdx.x == 0) a.pair_loss[m] = s;
+    return;
+  }
+  double tot[10];
+#pragma unroll
+  for (int r = 0; r < 10; ++r) tot[r] = block_sum(acc[r], red);
+  if (threadIdx.x != 0) return;
+  a.pair_loss[m] = tot[9];
+  // chain rule: F = Kj^-T E Ki^-1, E = [t_ij]_x R_ij, R_ij = R_j R_i^T, t_ij = t_j - R_ij t_i
+  M3 GF;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) GF.a[r][c] = tot[3 * r + c];
+  const M3 GE = mul(mul(pg.Kj, GF), tr(pg.Ki));
+  const M3 GKi = mul(tr(mul(tr(pg.Kj), pg.E)), GF);
+  const M3 GKjT = mul(GF, tr(mul(pg.E, pg.Ki)));
+  const double fi2 = ci.f * ci.f, fj2 = cj.f * cj.f;
+  // d(Ki^-1)/df_i and d(Kj^-T)/df_j contracted with the gradients, times df/dphi = f
+  const double gphi_i = (-(GKi.a[0][0] + GKi.a[1][1]) / fi2 + (GKi.a[0][2] * ci.cx + GKi.a[1][2] * ci.cy) / fi2) * ci.f;
+  const double gphi_j =
+      (-(GKjT.a[0][0] + GKjT.a[1][1]) / fj2 + (GKjT.a[2][0] * cj.cx + GKjT.a[2][1] * cj.cy) / fj2) * cj.f;
+  const M3 Mt = mul(GE, tr(pg.Rij));
+  const double gt[3] = {Mt.a[2][1] - Mt.a[1][2], Mt.a[0][2] - Mt.a[2][0], Mt.a[1][0] - Mt.a[0][1]};
+  M3 GR = mul(tr(skew3(pg.tij)), GE);
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) GR.a[r][c] -= gt[r] * ci.t[c];
+  const M3 gRj = mul(GR, ci.R);
+  const M3 gRi = mul(tr(GR), cj.R);
+  double* out = a.pair_grad + 16 * (int64_t)m;
+  // dR/dq for each camera, contracted with its rotation gradient
+  for (int side = 0; side < 2; ++side) {
+    const double* q = (side == 0 ? a.p + 8 * i : a.p + 8 * j);
+    const M3& gRs = side == 0 ? gRi : gRj;
+    const double w = q[0], x = q[1], y = q[2], z = q[3];
+    const double n2 = w * w + x * x + y * y + z * z;
+    const M3 N = quat_num(q);
+    const M3 dN[4] = {
+        {{{2 * w, -2 * z, 2 * y}, {2 * z, 2 * w, -2 * x}, {-2 * y, 2 * x, 2 * w}}},
+        {{{2 * x, 2 * y, 2 * z}, {2 * y, -2 * x, -2 * w}, {2 * z, 2 * w, -2 * x}}},
+        {{{-2 * y, 2 * x, 2 * w}, {2 * x, 2 * y, 2 * z}, {-2 * w, 2 * z, -2 * y}}},
+        {{{-2 * z, -2 * w, 2 * x}, {2 * w, -2 * z, 2 * y}, {2 * x, 2 * y, 2 * z}}},
+    };
+    for (int qa = 0; qa < 4; ++qa) {
+      double s = 0.0;
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) s += (dN[qa].a[r][c] * n2 - N.a[r][c] * 2.0 * q[qa]) * gRs.a[r][c];
+      out[8 * side + qa] = s / (n2 * n2);
+    }
+  }
+  // translations: dL/dt_j = gt, dL/dt_i = -R_ij^T gt
+  for (int r = 0; r < 3; ++r) {
+    out[8 + 4 + r] = gt[r];
+    out[4 + r] = -(pg.Rij.a[0][r] * gt[0] + pg.Rij.a[1][r] * gt[1] + pg.Rij.a[2][r] * gt[2]);
+  }
+  out[7] = gphi_i;
+  out[15] = gphi_j;
+}
+
+// One workgroup: weight table, total weight and learning rate from the bin counts.
+__global__ __launch_bounds__(256) void ga_table_kernel(const uint32_t* hist, double alpha, int lr_bin1, int lr_bin2,
+                                                       double lr0, double lr1, double lr2, double* table,
+                                                       double* scal) {
+  __shared__ double red[4];
+  __shared__ double dens[kGaBins + 1];
+  __shared__ uint64_t cum[kGaBins + 1];
+  double K = 0.0;
+  for (int b = 0; b <= kGaBins; ++b) K += (double)hist[b];  // every thread, same order
+  const double h = 1.0 / kGaBinsPerPixel;
+  for (int b = threadIdx.x; b <= kGaBins; b += 256) dens[b] = b < kGaBins && K > 0.0 ? (double)hist[b] / (K * h) : 0.0;
+  __syncthreads();
+  double part = 0.0;
+  for (int b = threadIdx.x; b <= kGaBins; b += 256) part += (double)hist[b] * dens[b];
+  const double avg = block_sum(part, red) / (K > 0.0 ? K : 1.0);
+  for (int b = threadIdx.x; b <= kGaBins; b += 256) table[b] = avg > 0.0 ? pow(dens[b] / avg, alpha) : 1.0;
+  __syncthreads();
+  double wp = 0.0;
+  for (int b = threadIdx.x; b <= kGaBins; b += 256) wp += (double)hist[b] * table[b];
+  const double W = block_sum(wp, red);
+  if (threadIdx.x == 0) {
+    uint64_t c = 0;
+    for (int b = 0; b <= kGaBins; ++b) {
+      c += hist[b];
+      cum[b] = c;
+    }
+    const uint64_t rank = (c + 1) / 2;
+    int mb = 0;
+    while (mb < kGaBins && cum[mb] < rank) ++mb;
+    scal[0] = mb < lr_bin1 ? lr0 : (mb < lr_bin2 ? lr1 : lr2);
+    scal[1] = W;
+    scal[2] = (double)mb;
+  }
+}
+
+// One thread per camera: gradient = sum over the camera's pair sides / W, then Adam.
+__global__ __launch_bounds__(256) void ga_adam_kernel(GaParams a, int n_cams, int step, double beta1, double beta2,
+                                                      double eps) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= n_cams) return;
+  double g[8] = {};
+  for (int e = a.inc_off[n]; e < a.inc_off[n + 1]; ++e) {
+    const int side = a.inc[e] & 1;
+    const double* src = a.pair_grad + 16 * (int64_t)(a.inc[e] >> 1) + 8 * side;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) g[r] += src[r];
+  }
+  const double W = a.scal[1], lr = a.scal[0];
+  const double invW = W > 0.0 ? 1.0 / W : 0.0;
+  const double c1 = 1.0 - pow(beta1, (double)step), c2 = 1.0 - pow(beta2, (double)step);
+  double* p = a.p + 8 * n;
+  double* mo = a.adam + 16 * n;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const double gr = g[r] * invW;
+    mo[r] = beta1 * mo[r] + (1.0 - beta1) * gr;
+    mo[8 + r] = beta2 * mo[8 + r] + (1.0 - beta2) * gr * gr;
+    p[r] -= lr * (mo[r] / c1) / (sqrt(mo[8 + r] / c2) + eps);
+  }
+}
+
+// One workgroup: loss = sum of the pair sums / W (fixed order per thread, then a tree).
+__global__ __launch_bounds__(256) void ga_loss_kernel(const double* pair_loss, int n_pairs, const double* scal,
+                                                      double* out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int m = threadIdx.x; m < n_pairs; m += 256) s += pair_loss[m];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) *out = scal[1] > 0.0 ? t / scal[1] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void ga_out_kernel(const double* p, const double* f0, int n_cams, double* R_out,
+                                                     double* t_out, double* f_out) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= n_cams) return;
+  const double* q = p + 8 * n;
+  const M3 R = quat_rot(q);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) R_out[9 * n + 3 * r + c] = R.a[r][c];
+  for (int r = 0; r < 3; ++r) t_out[3 * n + r] = q[4 + r];
+  f_out[n] = f0[n] * exp(q[7]);
+}
+
+__global__ __launch_bounds__(256) void ga_weights_kernel(const uint8_t* bins, const double* table, int64_t n,
+                                                         float* w) {
+  for (int64_t k = blockIdx.x * 256ll + threadIdx.x; k < n; k += (int64_t)gridDim.x * 256) w[k] = (float)table[bins[k]];
+}
+
+__global__ __launch_bounds__(256) void ga_zero_u32_kernel(uint32_t* x, int n) {
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) x[k] = 0u;
+}
+
+// ------------------------------------------------------------------ launchers
+static unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+hipError_t launch_ga_init(const double* R0, const double* t0, int n_cams, double* p, double* adam, hipStream_t s) {
+  hipLaunchKernelGGL(ga_init_kernel, dim3(cdiv_u(n_cams, 256)), dim3(256), 0, s, R0, t0, n_cams, p, adam);
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_pairs(const GaParams& a, int n_pairs, int mode, hipStream_t s) {
+  if (n_pairs <= 0) return hipSuccess;
+  switch (mode) {
+    case GA_MODE_BINS: hipLaunchKernelGGL(ga_pair_kernel<GA_MODE_BINS>, dim3(n_pairs), dim3(256), 0, s, a); break;
+    case GA_MODE_GRAD: hipLaunchKernelGGL(ga_pair_kernel<GA_MODE_GRAD>, dim3(n_pairs), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL(ga_pair_kernel<GA_MODE_LOSS>, dim3(n_pairs), dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_table(const uint32_t* hist, double alpha, int lr_bin1, int lr_bin2, double lr0, double lr1,
+                           double lr2, double* table, double* scal, hipStream_t s) {
+  hipLaunchKernelGGL(ga_table_kernel, dim3(1), dim3(256), 0, s, hist, alpha, lr_bin1, lr_bin2, lr0, lr1, lr2, table,
+                     scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_adam(const GaParams& a, int n_cams, int step, double beta1, double beta2, double eps,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(ga_adam_kernel, dim3(cdiv_u(n_cams, 256)), dim3(256), 0, s, a, n_cams, step, beta1, beta2, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_loss(const double* pair_loss, int n_pairs, const double* scal, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(ga_loss_kernel, dim3(1), dim3(256), 0, s, pair_loss, n_pairs, scal, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_out(const double* p, const double* f0, int n_cams, double* R_out, double* t_out, double* f_out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(ga_out_kernel, dim3(cdiv_u(n_cams, 256)), dim3(256), 0, s, p, f0, n_cams, R_out, t_out, f_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_weights(const uint8_t* bins, const double* table, int64_t n, float* w, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>(cdiv_u(n, 256), 65536);
+  hipLaunchKernelGGL(ga_weights_kernel, dim3(grid), dim3(256), 0, s, bins, table, n, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_zero_u32(uint32_t* x, int n, hipStream_t s) {
+  hipLaunchKernelGGL(ga_zero_u32_kernel, dim3(cdiv_u(n, 256)), dim3(256), 0, s, x, n);
+  return hipGetLastError();
+}
+
+}  // namespace vggtx

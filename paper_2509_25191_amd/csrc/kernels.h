@@ -112,4 +112,37 @@ hipError_t launch_embed_finish(const float* x, int Pd, const void* g, const void
                                int C, bool bf16_io, hipStream_t s);
 hipError_t launch_fill_hash_bf16(bf16* x, int64_t n, uint64_t seed, float scale, hipStream_t s);
 
+// ---- camera global alignment (ga.hip)
+constexpr int kGaBins = 200;               // residual histogram: bins of 1/kGaBinsPerPixel px over [0, 20)
+constexpr double kGaBinsPerPixel = 10.0;   // (+1 overflow bin for e >= 20 px)
+enum GaMode { GA_MODE_BINS = 0, GA_MODE_GRAD = 1, GA_MODE_LOSS = 2 };
+struct GaParams {
+  const int* pairs;         // [n_pairs, 2] camera indices (i, j)
+  const int64_t* offsets;   // [n_pairs + 1] correspondence offsets
+  const float* corr;        // [n_corr, 4] (u, v, u', v'), 16-byte aligned
+  const double* f0;         // [n_cams] initial focal lengths
+  const double* pp;         // [n_cams, 2] principal points
+  double* p;                // [n_cams, 8] parameters (q, t, phi)
+  double* adam;             // [n_cams, 16] first / second moments
+  uint8_t* bins;            // [n_corr] histogram bin of the initial residual
+  uint32_t* hist;           // [kGaBins + 1] bin counts
+  const double* table;      // [kGaBins + 1] weight of a bin
+  double* scal;             // [0] learning rate, [1] total weight W, [2] median bin
+  double* pair_grad;        // [n_pairs, 16] gradient w.r.t. (camera i, camera j) parameters
+  double* pair_loss;        // [n_pairs] sum_k w_k e_k
+  const int* inc_off;       // [n_cams + 1] CSR of the pair sides of each camera
+  const int* inc;           // [2 n_pairs] pair << 1 | side
+};
+hipError_t launch_ga_init(const double* R0, const double* t0, int n_cams, double* p, double* adam, hipStream_t s);
+hipError_t launch_ga_pairs(const GaParams& a, int n_pairs, int mode, hipStream_t s);
+hipError_t launch_ga_table(const uint32_t* hist, double alpha, int lr_bin1, int lr_bin2, double lr0, double lr1,
+                           double lr2, double* table, double* scal, hipStream_t s);
+hipError_t launch_ga_adam(const GaParams& a, int n_cams, int step, double beta1, double beta2, double eps,
+                          hipStream_t s);
+hipError_t launch_ga_loss(const double* pair_loss, int n_pairs, const double* scal, double* out, hipStream_t s);
+hipError_t launch_ga_out(const double* p, const double* f0, int n_cams, double* R_out, double* t_out, double* f_out,
+                         hipStream_t s);
+hipError_t launch_ga_weights(const uint8_t* bins, const double* table, int64_t n, float* w, hipStream_t s);
+hipError_t launch_ga_zero_u32(uint32_t* x, int n, hipStream_t s);
+
 }  // namespace vggtx

@@ -15,6 +15,7 @@
 #include <fstream>
 #include <sstream>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -785,6 +786,140 @@ vggtx_status embed_impl(vggtx_handle h, const float* images, int height, int wid
   return VGGTX_OK;
 }
 
+// -------------------------------------------------------------- global alignment
+struct GaWs {
+  double *p = nullptr, *adam = nullptr, *table = nullptr, *scal = nullptr, *pair_grad = nullptr, *pair_loss = nullptr;
+  int* pairs = nullptr;
+  int64_t* offsets = nullptr;
+  int *inc_off = nullptr, *inc = nullptr;
+  uint8_t* bins = nullptr;
+  uint32_t* hist = nullptr;
+  size_t total = 0;
+};
+
+GaWs ga_carve(int64_t n_cams, int64_t n_pairs, int64_t n_corr, char* base) {
+  GaWs w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? (void*)(base + off) : nullptr;
+    off += (size_t)round_up((int64_t)std::max<size_t>(bytes, 1), 256);
+    return p;
+  };
+  w.p = (double*)take(n_cams * 8 * 8);
+  w.adam = (double*)take(n_cams * 16 * 8);
+  w.table = (double*)take((kGaBins + 1) * 8);
+  w.scal = (double*)take(4 * 8);
+  w.hist = (uint32_t*)take((kGaBins + 1) * 4);
+  w.pair_grad = (double*)take(n_pairs * 16 * 8);
+  w.pair_loss = (double*)take(n_pairs * 8);
+  w.pairs = (int*)take(n_pairs * 2 * 4);
+  w.offsets = (int64_t*)take((n_pairs + 1) * 8);
+  w.inc_off = (int*)take((n_cams + 1) * 4);
+  w.inc = (int*)take(n_pairs * 2 * 4);
+  w.bins = (uint8_t*)take(n_corr);
+  w.total = off;
+  return w;
+}
+
+bool ga_bound_bin(double b, int* bin) {
+  const double x = b * kGaBinsPerPixel;
+  const double r = std::nearbyint(x);
+  if (!(std::fabs(x - r) <= 1e-9 * std::max(1.0, std::fabs(x))) || r < 0 || r > kGaBins) return false;
+  *bin = (int)r;
+  return true;
+}
+
+vggtx_status ga_impl(vggtx_handle h, const vggtx_ga_config* cfg, int n_cams, const double* R0, const double* t0,
+                     const double* f0, const double* pp, const int32_t* pairs, int n_pairs,
+                     const int64_t* corr_offsets, const float* corr, double* R_out, double* t_out, double* f_out,
+                     float* weights_out, double* loss_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  if (!cfg) return fail(VGGTX_E_INVALID, "config is null");
+  if (n_cams < 1 || n_cams > (1 << 24)) return fail(VGGTX_E_INVALID, "n_cams = %d", n_cams);
+  if (n_pairs < 0 || n_pairs > (1 << 28)) return fail(VGGTX_E_INVALID, "n_pairs = %d", n_pairs);
+  if (cfg->iterations < 0 || cfg->iterations > 1000000) return fail(VGGTX_E_INVALID, "iterations = %d", cfg->iterations);
+  int b1 = 0, b2 = 0;
+  if (!ga_bound_bin(cfg->bounds[0], &b1) || !ga_bound_bin(cfg->bounds[1], &b2) || b1 > b2)
+    return fail(VGGTX_E_INVALID, "bounds (%g, %g) must be increasing multiples of 0.1 in [0, 20]", cfg->bounds[0],
+                cfg->bounds[1]);
+  if (!(cfg->alpha >= 0.0) || !(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) || !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) ||
+      !(cfg->eps > 0.0) || !(cfg->lr[0] >= 0.0 && cfg->lr[1] >= 0.0 && cfg->lr[2] >= 0.0))
+    return fail(VGGTX_E_INVALID, "alpha, Adam constants or learning rates out of range");
+  if (n_pairs > 0 && (!pairs || !corr_offsets)) return fail(VGGTX_E_INVALID, "pairs / corr_offsets are null");
+  if (corr_offsets && corr_offsets[0] != 0) return fail(VGGTX_E_INVALID, "corr_offsets must start at 0");
+  for (int m = 0; m < n_pairs; ++m) {
+    const int i = pairs[2 * m], j = pairs[2 * m + 1];
+    if (i < 0 || j < 0 || i >= n_cams || j >= n_cams || i == j)
+      return fail(VGGTX_E_INVALID, "pair %d = (%d, %d) is not two distinct cameras of %d", m, i, j, n_cams);
+    if (corr_offsets[m + 1] < corr_offsets[m]) return fail(VGGTX_E_INVALID, "corr_offsets decrease at %d", m);
+  }
+  const int64_t n_corr = n_pairs > 0 ? corr_offsets[n_pairs] : 0;
+  const void* dptr[7] = {R0, t0, f0, pp, R_out, t_out, f_out};
+  for (int k = 0; k < 7; ++k)
+    if (!dptr[k] || (uintptr_t)dptr[k] % 8) return fail(VGGTX_E_INVALID, "camera pointer %d is null or misaligned", k);
+  if (n_corr > 0 && (!corr || (uintptr_t)corr % 16)) return fail(VGGTX_E_INVALID, "corr is null or not 16-byte aligned");
+  if ((weights_out && (uintptr_t)weights_out % 4) || (loss_out && (uintptr_t)loss_out % 8))
+    return fail(VGGTX_E_INVALID, "weights_out / loss_out misaligned");
+  const GaWs need = ga_carve(n_cams, n_pairs, n_corr, nullptr);
+  if (!ws || ws_bytes < need.total)
+    return fail(VGGTX_E_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need.total);
+  if ((uintptr_t)ws % 256) return fail(VGGTX_E_INVALID, "workspace must be 256-byte aligned");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+
+  const GaWs w = ga_carve(n_cams, n_pairs, n_corr, (char*)ws);
+  hipStream_t st = (hipStream_t)stream;
+  // incidence of every camera: (pair << 1 | side), pairs in order
+  std::vector<int> inc_off(n_cams + 1, 0), inc(2 * (size_t)n_pairs);
+  for (int m = 0; m < n_pairs; ++m) {
+    ++inc_off[pairs[2 * m] + 1];
+    ++inc_off[pairs[2 * m + 1] + 1];
+  }
+  for (int n = 0; n < n_cams; ++n) inc_off[n + 1] += inc_off[n];
+  {
+    std::vector<int> fill(inc_off.begin(), inc_off.end() - 1);
+    for (int m = 0; m < n_pairs; ++m) {
+      inc[fill[pairs[2 * m]]++] = m << 1;
+      inc[fill[pairs[2 * m + 1]]++] = (m << 1) | 1;
+    }
+  }
+  if (n_pairs > 0) {
+    VGGTX_HIP(hipMemcpyAsync(w.pairs, pairs, (size_t)n_pairs * 2 * 4, hipMemcpyHostToDevice, st));
+    VGGTX_HIP(hipMemcpyAsync(w.offsets, corr_offsets, (size_t)(n_pairs + 1) * 8, hipMemcpyHostToDevice, st));
+    VGGTX_HIP(hipMemcpyAsync(w.inc, inc.data(), inc.size() * 4, hipMemcpyHostToDevice, st));
+  }
+  VGGTX_HIP(hipMemcpyAsync(w.inc_off, inc_off.data(), inc_off.size() * 4, hipMemcpyHostToDevice, st));
+  VGGTX_HIP(hipStreamSynchronize(st));
+
+  GaParams a;
+  memset(&a, 0, sizeof(a));
+  a.pairs = w.pairs; a.offsets = w.offsets; a.corr = corr; a.f0 = f0; a.pp = pp;
+  a.p = w.p; a.adam = w.adam; a.bins = w.bins; a.hist = w.hist; a.table = w.table; a.scal = w.scal;
+  a.pair_grad = w.pair_grad; a.pair_loss = w.pair_loss; a.inc_off = w.inc_off; a.inc = w.inc;
+  VGGTX_HIP(launch_ga_init(R0, t0, n_cams, w.p, w.adam, st));
+  VGGTX_HIP(launch_ga_zero_u32(w.hist, kGaBins + 1, st));
+  {
+    Span sp(h, VGGTX_K_OTHER, 0.0, st);
+    VGGTX_HIP(launch_ga_pairs(a, n_pairs, GA_MODE_BINS, st));
+  }
+  VGGTX_HIP(launch_ga_table(w.hist, cfg->alpha, b1, b2, cfg->lr[0], cfg->lr[1], cfg->lr[2], w.table, w.scal, st));
+  for (int it = 0; it < cfg->iterations; ++it) {
+    {
+      Span sp(h, VGGTX_K_OTHER, 0.0, st);
+      VGGTX_HIP(launch_ga_pairs(a, n_pairs, GA_MODE_GRAD, st));
+    }
+    if (loss_out) VGGTX_HIP(launch_ga_loss(w.pair_loss, n_pairs, w.scal, loss_out + it, st));
+    VGGTX_HIP(launch_ga_adam(a, n_cams, it + 1, cfg->beta1, cfg->beta2, cfg->eps, st));
+  }
+  if (loss_out) {
+    VGGTX_HIP(launch_ga_pairs(a, n_pairs, GA_MODE_LOSS, st));
+    VGGTX_HIP(launch_ga_loss(w.pair_loss, n_pairs, w.scal, loss_out + cfg->iterations, st));
+  }
+  VGGTX_HIP(launch_ga_out(w.p, f0, n_cams, R_out, t_out, f_out, st));
+  if (weights_out) VGGTX_HIP(launch_ga_weights(w.bins, w.table, n_corr, weights_out, st));
+  return VGGTX_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C-ABI
@@ -902,6 +1037,68 @@ vggtx_status vggtx_embed(vggtx_handle h, const float* images, int height, int wi
                          int n_scenes, const vggtx_embed_w* w, float* tokens, vggtx_prec prec, void* ws,
                          size_t ws_bytes, void* stream) {
   return embed_impl(h, images, height, width, frame_offsets, n_scenes, w, tokens, prec, ws, ws_bytes, stream);
+}
+
+void vggtx_ga_config_default(vggtx_ga_config* cfg) {
+  if (!cfg) return;
+  cfg->iterations = 300;
+  cfg->lr[0] = 5e-4; cfg->lr[1] = 1e-3; cfg->lr[2] = 1e-2;
+  cfg->bounds[0] = 2.5; cfg->bounds[1] = 7.5;
+  cfg->alpha = 0.5;
+  cfg->beta1 = 0.9; cfg->beta2 = 0.999; cfg->eps = 1e-8;
+}
+
+vggtx_status vggtx_ga_select_pairs(const double* R, int n_cams, double max_angle_deg, int32_t* pairs, int max_pairs,
+                                   int* n_pairs) {
+  if (!R || !n_pairs) return fail(VGGTX_E_INVALID, "R / n_pairs is null");
+  if (n_cams < 0) return fail(VGGTX_E_INVALID, "n_cams = %d", n_cams);
+  const double cos_lim = std::cos(max_angle_deg * 3.14159265358979323846 / 180.0);
+  std::vector<double> z(3 * (size_t)n_cams);
+  for (int n = 0; n < n_cams; ++n) {
+    const double* r = R + 9 * (size_t)n + 6;
+    const double nn = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(nn > 0.0)) return fail(VGGTX_E_INVALID, "camera %d has a zero optical axis", n);
+    for (int k = 0; k < 3; ++k) z[3 * n + k] = r[k] / nn;
+  }
+  int64_t count = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1 && (!pairs || count == 0)) break;
+    if (pass == 1 && count > max_pairs)
+      return fail(VGGTX_E_INVALID, "%lld pairs do not fit max_pairs = %d", (long long)count, max_pairs);
+    int64_t c = 0;
+    for (int i = 0; i < n_cams; ++i)
+      for (int j = i + 1; j < n_cams; ++j) {
+        const double d = z[3 * i] * z[3 * j] + z[3 * i + 1] * z[3 * j + 1] + z[3 * i + 2] * z[3 * j + 2];
+        if (d > cos_lim) {
+          if (pass == 1) {
+            pairs[2 * c] = i;
+            pairs[2 * c + 1] = j;
+          }
+          ++c;
+        }
+      }
+    count = c;
+  }
+  if (count > INT32_MAX) return fail(VGGTX_E_UNSUPPORTED, "too many pairs");
+  *n_pairs = (int)count;
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_ga_workspace_size(vggtx_handle h, int n_cams, int n_pairs, int64_t n_corr, size_t* bytes) {
+  if (!h || !bytes) return fail(VGGTX_E_INVALID, "handle / bytes is null");
+  if (n_cams < 1 || n_pairs < 0 || n_corr < 0) return fail(VGGTX_E_INVALID, "n_cams %d, n_pairs %d, n_corr %lld",
+                                                          n_cams, n_pairs, (long long)n_corr);
+  *bytes = ga_carve(n_cams, n_pairs, n_corr, nullptr).total;
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_ga_align(vggtx_handle h, const vggtx_ga_config* cfg, int n_cams, const double* R0,
+                            const double* t0, const double* f0, const double* pp, const int32_t* pairs, int n_pairs,
+                            const int64_t* corr_offsets, const float* corr, double* R_out, double* t_out,
+                            double* f_out, float* weights_out, double* loss_out, void* ws, size_t ws_bytes,
+                            void* stream) {
+  return ga_impl(h, cfg, n_cams, R0, t0, f0, pp, pairs, n_pairs, corr_offsets, corr, R_out, t_out, f_out,
+                 weights_out, loss_out, ws, ws_bytes, stream);
 }
 
 vggtx_status vggtx_attn_workspace_size(vggtx_handle h, const int32_t* seq_offsets, int n_seq, int H, int D,

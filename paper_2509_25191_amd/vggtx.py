@@ -18,6 +18,7 @@ __all__ = [
     "aggregate", "aggregate_varlen", "block", "attn_workspace_size", "attn_frame", "attn_global",
     "quantize_fp8", "status_str", "last_error", "BLOCK_FIELDS", "timing_enable", "timing_read", "timing_poll",
     "autotune_workspace_size", "autotune", "EmbedW", "EMBED_FIELDS", "embed_workspace_size", "embed",
+    "GaConfig", "ga_config_default", "ga_select_pairs", "ga_workspace_size", "ga_align",
     "K_ATTN_GLOBAL", "K_ATTN_FRAME", "K_GEMM", "K_OTHER",
 ]
 
@@ -64,6 +65,12 @@ class EmbedW(ctypes.Structure):
                 ("cam", ctypes.c_void_p), ("agg_reg", ctypes.c_void_p)]
 
 
+class GaConfig(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("lr", ctypes.c_double * 3), ("bounds", ctypes.c_double * 2),
+                ("alpha", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
 class Layout(ctypes.Structure):
     _fields_ = [("token_stride", ctypes.c_int64), ("head_stride", ctypes.c_int64)]
 
@@ -99,6 +106,11 @@ def load():
         "vggtx_autotune": [vp, i32, i32, vp, sz, vp, ctypes.POINTER(i32)],
         "vggtx_embed_workspace_size": [vp, i32, i32, i32, i32, ctypes.POINTER(sz)],
         "vggtx_embed": [vp, vp, i32, i32, P_i32, i32, ctypes.POINTER(EmbedW), vp, i32, vp, sz, vp],
+        "vggtx_ga_config_default": [ctypes.POINTER(GaConfig)],
+        "vggtx_ga_select_pairs": [vp, i32, ctypes.c_double, P_i32, i32, ctypes.POINTER(i32)],
+        "vggtx_ga_workspace_size": [vp, i32, i32, i64, ctypes.POINTER(sz)],
+        "vggtx_ga_align": [vp, ctypes.POINTER(GaConfig), i32, vp, vp, vp, vp, P_i32, i32,
+                           ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp, vp, vp, vp, sz, vp],
         "vggtx_timing_enable": [vp, i32],
         "vggtx_timing_read": [vp, ctypes.POINTER(Timing), ctypes.POINTER(ctypes.c_int64)],
         "vggtx_timing_poll": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -110,6 +122,7 @@ def load():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = ctypes.c_char_p if name in ("vggtx_status_str", "vggtx_last_error") else ctypes.c_int
+    L.vggtx_ga_config_default.restype = None
     _lib = L
     return L
 
@@ -310,6 +323,53 @@ def embed(h, images: torch.Tensor, params: Dict[str, object], prec: int, frame_o
     _check(load().vggtx_embed(h, _ptr(images), height, width, _i32_array(frame_offsets), len(frame_offsets) - 1,
                               ctypes.byref(ew), _ptr(out), int(prec), _ptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+def ga_config_default() -> GaConfig:
+    cfg = GaConfig()
+    load().vggtx_ga_config_default(ctypes.byref(cfg))
+    return cfg
+
+
+def ga_select_pairs(R, max_angle_deg: float = 30.0):
+    """R: host float64 array-like [N, 3, 3] -> list of (i, j) pairs (host-side rule)."""
+    import numpy as np
+    Rh = np.ascontiguousarray(np.asarray(R, dtype=np.float64))
+    n = ctypes.c_int()
+    _check(load().vggtx_ga_select_pairs(Rh.ctypes.data_as(ctypes.c_void_p), len(Rh), float(max_angle_deg), None, 0,
+                                        ctypes.byref(n)))
+    buf = (ctypes.c_int32 * max(1, 2 * n.value))()
+    _check(load().vggtx_ga_select_pairs(Rh.ctypes.data_as(ctypes.c_void_p), len(Rh), float(max_angle_deg), buf,
+                                        n.value, ctypes.byref(n)))
+    return [(buf[2 * k], buf[2 * k + 1]) for k in range(n.value)]
+
+
+def ga_workspace_size(h, n_cams: int, n_pairs: int, n_corr: int) -> int:
+    n = ctypes.c_size_t()
+    _check(load().vggtx_ga_workspace_size(h, int(n_cams), int(n_pairs), int(n_corr), ctypes.byref(n)))
+    return n.value
+
+
+def ga_align(h, R0: torch.Tensor, t0: torch.Tensor, f0: torch.Tensor, pp: torch.Tensor, pairs: Sequence,
+             corr_offsets: Sequence[int], corr: torch.Tensor, cfg: Optional[GaConfig] = None, weights: bool = True,
+             losses: bool = True, ws: Optional[torch.Tensor] = None, stream=None):
+    """Global alignment.  Camera tensors float64 on the device, corr float32 [K, 4] on the device; pairs and
+    corr_offsets on the host.  Returns (R, t, f, weights or None, losses or None)."""
+    cfg = cfg if cfg is not None else ga_config_default()
+    N, P = R0.shape[0], len(pairs)
+    K = int(corr_offsets[-1]) if P else 0
+    dev = R0.device
+    R, t, f = torch.empty_like(R0), torch.empty_like(t0), torch.empty_like(f0)
+    w = torch.empty(max(1, K), dtype=torch.float32, device=dev) if weights else None
+    lo = torch.empty(cfg.iterations + 1, dtype=torch.float64, device=dev) if losses else None
+    if ws is None:
+        ws = _alloc_ws(ga_workspace_size(h, N, P, K), dev)
+    pa = (ctypes.c_int32 * max(1, 2 * P))(*[int(v) for pr in pairs for v in pr])
+    off = (ctypes.c_int64 * (P + 1))(*[int(v) for v in corr_offsets]) if P else None
+    _check(load().vggtx_ga_align(h, ctypes.byref(cfg), N, _ptr(R0), _ptr(t0), _ptr(f0), _ptr(pp), pa, P, off,
+                                 _ptr(corr), _ptr(R), _ptr(t), _ptr(f), _ptr(w), _ptr(lo), _ptr(ws), ws.numel(),
+                                 _stream(stream)))
+    return R, t, f, (w[:K] if w is not None else None), lo
 
 
 def timing_enable(h, enable: bool = True) -> None:

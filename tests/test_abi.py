@@ -78,3 +78,22 @@ def test_front_end_rejects_bad_calls_without_device():
     off = (ctypes.c_int32 * 2)(0, 4)
     assert lib.vggtx_embed(None, None, 518, 518, off, 1, None, None, vg.BF16, None, 0, None) == 1
     assert "null" in vg.last_error()
+
+
+def test_ga_pair_selection_is_host_side_and_matches_oracle():
+    """vggtx_ga_select_pairs runs on the host (no device needed)."""
+    import numpy as np
+    import synth
+    from oracle import ga
+    rng = np.random.default_rng(3)
+    _, init = synth.gen_ga_cameras(rng, 40, arc_deg=300.0, rot_noise_deg=3.0)
+    got = vg.ga_select_pairs(init["R"], 30.0)
+    want = [tuple(p) for p in ga.select_pairs(init["R"], 30.0).tolist()]
+    assert got == want and len(got) > 40
+    lib = vg.load()
+    n = ctypes.c_int()
+    small = (ctypes.c_int32 * 2)()
+    Rh = np.ascontiguousarray(init["R"])
+    assert lib.vggtx_ga_select_pairs(Rh.ctypes.data_as(ctypes.c_void_p), 40, 30.0, small, 1, ctypes.byref(n)) == 1
+    cfg = vg.ga_config_default()
+    assert cfg.iterations == 300 and list(cfg.lr) == [5e-4, 1e-3, 1e-2] and list(cfg.bounds) == [2.5, 7.5]

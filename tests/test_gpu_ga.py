@@ -1,0 +1,127 @@
+"""Parity of the HIP global alignment (Sec. 3.3) with the FP64 oracle: the
+weights of Eq. (weight), the learning-rate rule of Eq. (lr), the loss history
+of Eq. (epi) and the refined cameras, plus host-side rejection of bad calls."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import DEV
+from oracle import ga
+
+vg = pytest.importorskip("paper_2509_25191_amd.vggtx")
+pytestmark = pytest.mark.gpu
+
+
+def _dev64(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float64)).to(DEV)
+
+
+def _problem(seed, n_cams, arc, per_pair, rot_noise=1.0, trans_noise=0.05, focal_noise=0.02, outliers=0.2):
+    rng = np.random.default_rng(seed)
+    true, init = synth.gen_ga_cameras(rng, n_cams, arc_deg=arc, rot_noise_deg=rot_noise, trans_noise=trans_noise,
+                                      focal_noise=focal_noise)
+    pairs = ga.select_pairs(init["R"], 30.0)
+    corr, off = synth.gen_ga_corr(rng, true, pairs, per_pair, outlier_frac=outliers)
+    return true, init, pairs, corr, off
+
+
+def _run(h, init, pairs, corr, off, iterations):
+    cfg = vg.ga_config_default()
+    cfg.iterations = iterations
+    return vg.ga_align(h.h, _dev64(init["R"]), _dev64(init["t"]), _dev64(init["f"]), _dev64(init["c"]),
+                       pairs.tolist(), off.tolist(), torch.from_numpy(corr).to(DEV), cfg)
+
+
+def _compare(got, ref, tol):
+    R, t, f, w, lo = (x.cpu().numpy() if x is not None else None for x in got)
+    Rr, tr, fr, wr, lor, _ = ref
+    eR = np.abs(R - Rr).max()
+    et = np.abs(t - tr).max() / np.abs(tr).max()
+    ef = np.abs(f / fr - 1).max()
+    el = np.abs(lo - lor).max() / np.abs(lor).max()
+    ew = np.abs(w - wr).max() / max(np.abs(wr).max(), 1e-30)
+    print(f"  R {eR:.2e}  t {et:.2e}  f {ef:.2e}  loss {el:.2e}  weights {ew:.2e}; "
+          f"loss {lor[0]:.4f} -> {lor[-1]:.4f}", flush=True)
+    assert eR < tol and et < tol and ef < tol and el < tol
+    assert ew < 1e-6  # weights stored as float32
+
+
+@pytest.mark.parametrize("rot_noise,trans_noise,want_lr", [(0.2, 0.01, 1e-3), (1.0, 0.05, 1e-2), (4.0, 0.3, 1e-2),
+                                                         (0.05, 0.002, 5e-4)])
+def test_ga_parity_small(rot_noise, trans_noise, want_lr):
+    """8 cameras on an 80-degree arc, 200 correspondences per pair, 20%
+    outliers; initial-error levels that select each learning rate.  50
+    iterations agree to rounding; beyond about 100 iterations at the large
+    rate the non-smooth loss (|x'^T F x|) makes both float64 trajectories
+    drift apart from rounding differences alone, so the 300-iteration run is
+    compared by its final loss."""
+    true, init, pairs, corr, off = _problem(31, 8, 80.0, 200, rot_noise, trans_noise)
+    ref = ga.align(init["R"], init["t"], init["f"], init["c"], pairs, off, corr, iterations=50)
+    print(f"GA small rot_noise={rot_noise} pairs={len(pairs)} corr={off[-1]} lr={ref[5]}", flush=True)
+    assert ref[5] == want_lr
+    h = vg.Handle(0, dim=256, heads=4, mlp_hidden=1024)
+    got = _run(h, init, pairs, corr, off, 50)
+    torch.cuda.synchronize()
+    _compare(got, ref, 1e-9)
+    ref300 = ga.align(init["R"], init["t"], init["f"], init["c"], pairs, off, corr, iterations=300)
+    lo = _run(h, init, pairs, corr, off, 300)[4].cpu().numpy()
+    print(f"  300 iterations: final loss {lo[-1]:.5f} (oracle {ref300[4][-1]:.5f}), start {lo[0]:.5f}", flush=True)
+    assert abs(lo[-1] / ref300[4][-1] - 1) < 0.05
+    h.close()
+
+
+def test_ga_parity_ring_4096_per_pair():
+    """100 cameras on a full ring (about 800 pairs under 30 degrees), 4096
+    correspondences per pair as in the paper; 5 iterations against the oracle."""
+    true, init, pairs, corr, off = _problem(32, 100, 360.0, 4096)
+    print(f"GA ring: pairs={len(pairs)} corr={off[-1]}", flush=True)
+    ref = ga.align(init["R"], init["t"], init["f"], init["c"], pairs, off, corr, iterations=5)
+    h = vg.Handle(0, dim=256, heads=4, mlp_hidden=1024)
+    got = _run(h, init, pairs, corr, off, 5)
+    torch.cuda.synchronize()
+    _compare(got, ref, 1e-9)
+    h.close()
+
+
+def test_ga_zero_iterations_and_empty_pairs():
+    true, init, pairs, corr, off = _problem(33, 5, 40.0, 50)
+    h = vg.Handle(0, dim=256, heads=4, mlp_hidden=1024)
+    R, t, f, w, lo = _run(h, init, pairs, corr, off, 0)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(R.cpu().numpy(), init["R"], atol=1e-14)
+    np.testing.assert_array_equal(t.cpu().numpy(), init["t"])
+    np.testing.assert_array_equal(f.cpu().numpy(), init["f"])
+    ref = ga.align(init["R"], init["t"], init["f"], init["c"], pairs, off, corr, iterations=0)
+    assert abs(lo.cpu().numpy()[0] - ref[4][0]) < 1e-12 * ref[4][0]
+    # no pairs: the cameras come back unchanged and the loss is 0
+    cfg = vg.ga_config_default()
+    R2, t2, f2, w2, lo2 = vg.ga_align(h.h, _dev64(init["R"]), _dev64(init["t"]), _dev64(init["f"]),
+                                      _dev64(init["c"]), [], [0], torch.zeros((1, 4), device=DEV), cfg)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(t2.cpu().numpy(), init["t"])
+    assert float(lo2.abs().max()) == 0.0
+    h.close()
+
+
+def test_ga_rejected_calls_enqueue_nothing():
+    true, init, pairs, corr, off = _problem(34, 4, 30.0, 20)
+    h = vg.Handle(0, dim=256, heads=4, mlp_hidden=1024)
+    cd = torch.from_numpy(corr).to(DEV)
+    args = [_dev64(init[k]) for k in ("R", "t", "f", "c")]
+    for bad_pairs, bad_off in (([(0, 0)] + pairs.tolist()[1:], off.tolist()),
+                               (pairs.tolist(), [0] + [int(off[-1])] + off.tolist()[2:]),
+                               ([(0, 9)] + pairs.tolist()[1:], off.tolist())):
+        with pytest.raises(vg.VggtxError) as e:
+            vg.ga_align(h.h, *args, bad_pairs, bad_off, cd)
+        assert e.value.status == 1
+    small = torch.empty(256, dtype=torch.uint8, device=DEV)
+    with pytest.raises(vg.VggtxError) as e:
+        vg.ga_align(h.h, *args, pairs.tolist(), off.tolist(), cd, ws=small)
+    assert e.value.status == 3
+    cfg = vg.ga_config_default()
+    cfg.bounds[0] = 2.55
+    with pytest.raises(vg.VggtxError) as e:
+        vg.ga_align(h.h, *args, pairs.tolist(), off.tolist(), cd, cfg=cfg)
+    assert e.value.status == 1
+    h.close()
