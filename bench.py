@@ -247,6 +247,110 @@ def bench_embed(args, dev):
     print(json.dumps(res), flush=True)
 
 
+def ga_inputs(n_cams, per_pair, seed, dev):
+    """Cameras on a full ring looking at the origin (the predicted cameras are
+    the true ones perturbed: 1 degree rotation, 0.05 centre, 2% focal), pairs
+    under 30 degrees chosen by the library's host rule, and per pair
+    `per_pair` correspondences: points N(0, 0.7^2) projected into both true
+    cameras, 0.5 px noise, 20% outliers; drawn on the device."""
+    rng = np.random.default_rng(seed)
+    true, init = synth.gen_ga_cameras(rng, n_cams, arc_deg=360.0)
+    pairs = vg.ga_select_pairs(init["R"], 30.0)
+    P = len(pairs)
+    offsets = [per_pair * m for m in range(P + 1)]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    Rt = torch.from_numpy(true["R"]).to(dev); tt = torch.from_numpy(true["t"]).to(dev)
+    ft = torch.from_numpy(true["f"]).to(dev); ct = torch.from_numpy(true["c"]).to(dev)
+    pa = torch.tensor(pairs, dtype=torch.int64, device=dev)
+    corr = torch.empty((P * per_pair, 4), dtype=torch.float32, device=dev)
+    step = max(1, (1 << 24) // per_pair)
+    for m0 in range(0, P, step):
+        m1 = min(P, m0 + step)
+        n = (m1 - m0) * per_pair
+        X = torch.empty((m1 - m0, per_pair, 3), dtype=torch.float64, device=dev).normal_(0, 0.7, generator=gen)
+        cols = []
+        for side in (0, 1):
+            cam = pa[m0:m1, side]
+            Rc, tc = Rt[cam], tt[cam]
+            Xc = [sum(Rc[:, r, k][:, None] * X[..., k] for k in range(3)) + tc[:, r][:, None] for r in range(3)]
+            cols.append(ft[cam][:, None] * Xc[0] / Xc[2] + ct[cam][:, None, 0])
+            cols.append(ft[cam][:, None] * Xc[1] / Xc[2] + ct[cam][:, None, 1])
+        a = torch.stack(cols, -1).reshape(n, 4)
+        a += torch.empty_like(a).normal_(0, 0.5, generator=gen)
+        bad = torch.rand(n, device=dev, dtype=torch.float64, generator=gen) < 0.2
+        a[bad, 2:] = torch.rand((int(bad.sum()), 2), device=dev, dtype=torch.float64, generator=gen) * 518.0
+        corr[m0 * per_pair:m1 * per_pair] = a.float()
+    return init, pairs, offsets, corr
+
+
+def bench_ga(args, dev):
+    """Camera global alignment: N cameras, pairs under 30 degrees, 4096
+    correspondences per pair, the paper's 300 iterations."""
+    n_cams, per_pair = args.cameras, 4096
+    log(f"GA: generating {n_cams} cameras, {per_pair} correspondences per pair")
+    init, pairs, offsets, corr = ga_inputs(n_cams, per_pair, args.seed, dev)
+    P, K = len(pairs), offsets[-1]
+    log(f"GA: {P} pairs, {K} correspondences ({K * 16 / 1e9:.2f} GB)")
+    cams = [torch.from_numpy(np.ascontiguousarray(init[k])).to(dev) for k in ("R", "t", "f", "c")]
+    h = vg.Handle(0, dim=256, heads=4, mlp_hidden=1024)
+    ws = torch.empty(vg.ga_workspace_size(h.h, n_cams, P, K), dtype=torch.uint8, device=dev)
+    cfg = vg.ga_config_default()
+    for i in range(args.warmup):
+        vg.ga_align(h.h, *cams, pairs, offsets, corr, cfg, ws=ws)
+        torch.cuda.synchronize()
+        log(f"warmup run {i} done")
+    vg.timing_enable(h.h, True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(args.steps):
+        R, t, f, w, lo = vg.ga_align(h.h, *cams, pairs, offsets, corr, cfg, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    tm = vg.timing_read(h.h)
+    vg.timing_enable(h.h, False)
+    lo = lo.cpu().numpy()
+    log(f"GA: {args.steps} run(s) in {sec:.3f}s; loss {lo[0]:.4f} -> {lo[-1]:.4f}")
+    oth = tm["other"]
+    avg_ms = oth["ms"] / max(1, oth["launches"])
+    bytes_per_launch = K * 17.0  # float32 x 4 correspondence + uint8 weight bin, per pass
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    res = {
+        "metric": "global alignment: correspondence-iterations/s (300 Adam iterations, pairs under 30 deg, 4096 per pair)",
+        "value": K * cfg.iterations * args.steps / sec, "unit": "correspondence-iterations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (ring of cameras, projected points with 0.5 px noise and 20% outliers, seeded)",
+        "config": {"workload": f"ga_ring_N{n_cams}_4096perpair", "cameras": n_cams, "pairs": P,
+                   "correspondences": K, "iterations": cfg.iterations},
+        "loss_first_last": [float(lo[0]), float(lo[-1])],
+        "roofline": {"kernel": "ga_pair_kernel (residual + gradient pass)", "bound": "hbm", "achieved": achieved,
+                     "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms, "launches": oth["launches"]},
+    }
+    h.close()
+    if not args.no_cpu_baseline:
+        from oracle import ga as oga
+        sub = min(P, 64)
+        c_np = corr[:sub * per_pair].cpu().numpy()
+        off = np.arange(sub + 1) * per_pair
+        pr = np.array(pairs[:sub])
+        bins = oga.hist_bins(oga.all_residuals({k: init[k] for k in ("R", "t", "f", "c")}, pr, off, c_np))
+        _, table = oga.weight_table(bins)
+        p0 = {"q": oga.rot_to_quat(init["R"]), "t": init["t"].copy(), "phi": np.zeros(n_cams)}
+        t0 = time.perf_counter()
+        oga.gradient(p0, init["f"], init["c"], pr, off, c_np, table, bins)
+        oga.loss(p0, init["f"], init["c"], pr, off, c_np, table, bins)
+        tcpu = time.perf_counter() - t0
+        import threadpoolctl
+        cores = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] + [1])
+        res["cpu_baseline"] = {"value": sub * per_pair / tcpu, "unit": "correspondence-iterations/s",
+                               "cores": int(cores), "kind": "oracle",
+                               "sample": f"one oracle iteration (loss + gradient) over {sub} pairs x {per_pair} ({tcpu:.2f}s)"}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,8 +363,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 2 GiB device to device (calibrates HBM byte counters)")
-    ap.add_argument("--stage", choices=["aggregator", "embed"], default="aggregator",
-                    help="aggregator (default): the aggregator forward; embed: the patch-embedding front end")
+    ap.add_argument("--stage", choices=["aggregator", "embed", "ga"], default="aggregator",
+                    help="aggregator (default): the aggregator forward; embed: the patch-embedding front end; "
+                         "ga: camera global alignment")
+    ap.add_argument("--cameras", type=int, default=1000, help="--stage ga: number of cameras")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
@@ -271,6 +377,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.stage == "embed":
         bench_embed(args, dev)
+        return
+    if args.stage == "ga":
+        bench_ga(args, dev)
         return
     S, P = args.frames, P_TOKENS
     model = synth.ModelConfig()

@@ -16,9 +16,9 @@
 //   ga_init_kernel   parameters from the initial cameras, Adam state zeroed
 //   ga_pair_kernel   MODE_BINS: residual histogram bin of every correspondence
 //                    (initial cameras) and the global bin counts;
-//                    MODE_GRAD: per pair sum_k w_k e_k and the gradient of it
-//                    with respect to the 16 parameters of the two cameras;
-//                    MODE_LOSS: sum_k w_k e_k only
+//                    MODE_GRAD: per pair sum_k w_k e_k and its gradient with
+//                    respect to F; MODE_LOSS: sum_k w_k e_k only
+//   ga_chain_kernel  per pair: gradient w.r.t. the 16 parameters of the two cameras
 //   ga_table_kernel  weight per bin, total weight, learning rate (median bin)
 //   ga_adam_kernel   per camera: sum of its pairs' gradients / W, Adam step
 //   ga_loss_kernel   sum of the pair losses / W into the loss history
@@ -184,16 +184,19 @@ __global__ __launch_bounds__(256) void ga_pair_kernel(GaParams a) {
   const int m = blockIdx.x;
   const int i = a.pairs[2 * m], j = a.pairs[2 * m + 1];
   const int64_t k0 = a.offsets[m], k1 = a.offsets[m + 1];
-  const Cam ci = load_cam(a.p, a.f0, a.pp, i);
-  const Cam cj = load_cam(a.p, a.f0, a.pp, j);
-  const PairGeom pg = pair_geom(ci, cj);
+  M3 F;
+  {
+    const Cam ci = load_cam(a.p, a.f0, a.pp, i);
+    const Cam cj = load_cam(a.p, a.f0, a.pp, j);
+    F = pair_geom(ci, cj).F;
+  }
   const f32x4* corr = (const f32x4*)a.corr;
   if (MODE == GA_MODE_BINS) {
     for (int b = threadIdx.x; b <= kGaBins; b += 256) hist[b] = 0u;
     __syncthreads();
     for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
       double g[3];
-      const double e = residual(pg.F, corr[k], g, false);
+      const double e = residual(F, corr[k], g, false);
       const int b = e < (double)kGaBins / kGaBinsPerPixel ? (int)floor(e * kGaBinsPerPixel) : kGaBins;
       a.bins[k] = (uint8_t)b;
       atomicAdd(&hist[b], 1u);
@@ -209,7 +212,7 @@ __global__ __launch_bounds__(256) void ga_pair_kernel(GaParams a) {
     const double w = a.table[a.bins[k]];
     const f32x4 c = corr[k];
     double g[3];
-    const double e = residual(pg.F, c, g, MODE == GA_MODE_GRAD);
+    const double e = residual(F, c, g, MODE == GA_MODE_GRAD);
     acc[9] += w * e;
     if (MODE == GA_MODE_GRAD) {
       const double x0 = (double)c[0], x1 = (double)c[1];
@@ -232,12 +235,27 @@ __global__ __launch_bounds__(256) void ga_pair_kernel(GaParams a) {
   for (int r = 0; r < 10; ++r) tot[r] = block_sum(acc[r], red);
   if (threadIdx.x != 0) return;
   a.pair_loss[m] = tot[9];
-  // chain rule: F = Kj^-T E Ki^-1, E = [t_ij]_x R_ij, R_ij = R_j R_i^T, t_ij = t_j - R_ij t_i
+  double* gf = a.pair_gf + 9 * (int64_t)m;
+#pragma unroll
+  for (int r = 0; r < 9; ++r) gf[r] = tot[r];
+}
+
+// One thread per pair: chain rule from dL/dF to the 16 parameters of the two
+// cameras.  F = Kj^-T E Ki^-1, E = [t_ij]_x R_ij, R_ij = R_j R_i^T,
+// t_ij = t_j - R_ij t_i, R = N(q) / |q|^2, f = f0 exp(phi).
+__global__ __launch_bounds__(256) void ga_chain_kernel(GaParams a, int n_pairs) {
+  const int m = blockIdx.x * 256 + threadIdx.x;
+  if (m >= n_pairs) return;
+  const int i = a.pairs[2 * m], j = a.pairs[2 * m + 1];
+  const Cam ci = load_cam(a.p, a.f0, a.pp, i);
+  const Cam cj = load_cam(a.p, a.f0, a.pp, j);
+  const PairGeom pg = pair_geom(ci, cj);
   M3 GF;
+  const double* gf = a.pair_gf + 9 * (int64_t)m;
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) GF.a[r][c] = tot[3 * r + c];
+    for (int c = 0; c < 3; ++c) GF.a[r][c] = gf[3 * r + c];
   const M3 GE = mul(mul(pg.Kj, GF), tr(pg.Ki));
   const M3 GKi = mul(tr(mul(tr(pg.Kj), pg.E)), GF);
   const M3 GKjT = mul(GF, tr(mul(pg.E, pg.Ki)));
@@ -320,38 +338,44 @@ __global__ __launch_bounds__(256) void ga_table_kernel(const uint32_t* hist, dou
   }
 }
 
-// One thread per camera: gradient = sum over the camera's pair sides / W, then Adam.
+// One wave per camera: its pair sides are summed lane-strided (fixed order per
+// lane, then a fixed butterfly), scaled by 1/W, then one Adam step.
 __global__ __launch_bounds__(256) void ga_adam_kernel(GaParams a, int n_cams, int step, double beta1, double beta2,
                                                       double eps) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
+  const int n = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (n >= n_cams) return;
   double g[8] = {};
-  for (int e = a.inc_off[n]; e < a.inc_off[n + 1]; ++e) {
+  for (int e = a.inc_off[n] + lane; e < a.inc_off[n + 1]; e += 64) {
     const int side = a.inc[e] & 1;
     const double* src = a.pair_grad + 16 * (int64_t)(a.inc[e] >> 1) + 8 * side;
 #pragma unroll
     for (int r = 0; r < 8; ++r) g[r] += src[r];
   }
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) g[r] += __shfl_xor(g[r], o);
+  if (lane >= 8) return;
   const double W = a.scal[1], lr = a.scal[0];
   const double invW = W > 0.0 ? 1.0 / W : 0.0;
   const double c1 = 1.0 - pow(beta1, (double)step), c2 = 1.0 - pow(beta2, (double)step);
+  double gr = 0.0;
+#pragma unroll
+  for (int r = 0; r < 8; ++r)
+    if (lane == r) gr = g[r] * invW;
   double* p = a.p + 8 * n;
   double* mo = a.adam + 16 * n;
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const double gr = g[r] * invW;
-    mo[r] = beta1 * mo[r] + (1.0 - beta1) * gr;
-    mo[8 + r] = beta2 * mo[8 + r] + (1.0 - beta2) * gr * gr;
-    p[r] -= lr * (mo[r] / c1) / (sqrt(mo[8 + r] / c2) + eps);
-  }
+  mo[lane] = beta1 * mo[lane] + (1.0 - beta1) * gr;
+  mo[8 + lane] = beta2 * mo[8 + lane] + (1.0 - beta2) * gr * gr;
+  p[lane] -= lr * (mo[lane] / c1) / (sqrt(mo[8 + lane] / c2) + eps);
 }
 
 // One workgroup: loss = sum of the pair sums / W (fixed order per thread, then a tree).
-__global__ __launch_bounds__(256) void ga_loss_kernel(const double* pair_loss, int n_pairs, const double* scal,
-                                                      double* out) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(1024) void ga_loss_kernel(const double* pair_loss, int n_pairs, const double* scal,
+                                                       double* out) {
+  __shared__ double red[16];
   double s = 0.0;
-  for (int m = threadIdx.x; m < n_pairs; m += 256) s += pair_loss[m];
+  for (int m = threadIdx.x; m < n_pairs; m += 1024) s += pair_loss[m];
   const double t = block_sum(s, red);
   if (threadIdx.x == 0) *out = scal[1] > 0.0 ? t / scal[1] : 0.0;
 }
@@ -404,12 +428,18 @@ hipError_t launch_ga_table(const uint32_t* hist, double alpha, int lr_bin1, int 
 
 hipError_t launch_ga_adam(const GaParams& a, int n_cams, int step, double beta1, double beta2, double eps,
                           hipStream_t s) {
-  hipLaunchKernelGGL(ga_adam_kernel, dim3(cdiv_u(n_cams, 256)), dim3(256), 0, s, a, n_cams, step, beta1, beta2, eps);
+  hipLaunchKernelGGL(ga_adam_kernel, dim3(cdiv_u(n_cams, 4)), dim3(256), 0, s, a, n_cams, step, beta1, beta2, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_ga_chain(const GaParams& a, int n_pairs, hipStream_t s) {
+  if (n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(ga_chain_kernel, dim3(cdiv_u(n_pairs, 256)), dim3(256), 0, s, a, n_pairs);
   return hipGetLastError();
 }
 
 hipError_t launch_ga_loss(const double* pair_loss, int n_pairs, const double* scal, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(ga_loss_kernel, dim3(1), dim3(256), 0, s, pair_loss, n_pairs, scal, out);
+  hipLaunchKernelGGL(ga_loss_kernel, dim3(1), dim3(1024), 0, s, pair_loss, n_pairs, scal, out);
   return hipGetLastError();
 }
 

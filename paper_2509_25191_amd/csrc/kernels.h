@@ -128,6 +128,7 @@ struct GaParams {
   uint32_t* hist;           // [kGaBins + 1] bin counts
   const double* table;      // [kGaBins + 1] weight of a bin
   double* scal;             // [0] learning rate, [1] total weight W, [2] median bin
+  double* pair_gf;          // [n_pairs, 9] sum_k w_k de_k/dF
   double* pair_grad;        // [n_pairs, 16] gradient w.r.t. (camera i, camera j) parameters
   double* pair_loss;        // [n_pairs] sum_k w_k e_k
   const int* inc_off;       // [n_cams + 1] CSR of the pair sides of each camera
@@ -135,6 +136,7 @@ struct GaParams {
 };
 hipError_t launch_ga_init(const double* R0, const double* t0, int n_cams, double* p, double* adam, hipStream_t s);
 hipError_t launch_ga_pairs(const GaParams& a, int n_pairs, int mode, hipStream_t s);
+hipError_t launch_ga_chain(const GaParams& a, int n_pairs, hipStream_t s);
 hipError_t launch_ga_table(const uint32_t* hist, double alpha, int lr_bin1, int lr_bin2, double lr0, double lr1,
                            double lr2, double* table, double* scal, hipStream_t s);
 hipError_t launch_ga_adam(const GaParams& a, int n_cams, int step, double beta1, double beta2, double eps,

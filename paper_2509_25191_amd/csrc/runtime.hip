@@ -788,7 +788,8 @@ vggtx_status embed_impl(vggtx_handle h, const float* images, int height, int wid
 
 // -------------------------------------------------------------- global alignment
 struct GaWs {
-  double *p = nullptr, *adam = nullptr, *table = nullptr, *scal = nullptr, *pair_grad = nullptr, *pair_loss = nullptr;
+  double *p = nullptr, *adam = nullptr, *table = nullptr, *scal = nullptr, *pair_gf = nullptr, *pair_grad = nullptr,
+         *pair_loss = nullptr;
   int* pairs = nullptr;
   int64_t* offsets = nullptr;
   int *inc_off = nullptr, *inc = nullptr;
@@ -810,6 +811,7 @@ GaWs ga_carve(int64_t n_cams, int64_t n_pairs, int64_t n_corr, char* base) {
   w.table = (double*)take((kGaBins + 1) * 8);
   w.scal = (double*)take(4 * 8);
   w.hist = (uint32_t*)take((kGaBins + 1) * 4);
+  w.pair_gf = (double*)take(n_pairs * 9 * 8);
   w.pair_grad = (double*)take(n_pairs * 16 * 8);
   w.pair_loss = (double*)take(n_pairs * 8);
   w.pairs = (int*)take(n_pairs * 2 * 4);
@@ -895,7 +897,7 @@ vggtx_status ga_impl(vggtx_handle h, const vggtx_ga_config* cfg, int n_cams, con
   memset(&a, 0, sizeof(a));
   a.pairs = w.pairs; a.offsets = w.offsets; a.corr = corr; a.f0 = f0; a.pp = pp;
   a.p = w.p; a.adam = w.adam; a.bins = w.bins; a.hist = w.hist; a.table = w.table; a.scal = w.scal;
-  a.pair_grad = w.pair_grad; a.pair_loss = w.pair_loss; a.inc_off = w.inc_off; a.inc = w.inc;
+  a.pair_gf = w.pair_gf; a.pair_grad = w.pair_grad; a.pair_loss = w.pair_loss; a.inc_off = w.inc_off; a.inc = w.inc;
   VGGTX_HIP(launch_ga_init(R0, t0, n_cams, w.p, w.adam, st));
   VGGTX_HIP(launch_ga_zero_u32(w.hist, kGaBins + 1, st));
   {
@@ -908,6 +910,7 @@ vggtx_status ga_impl(vggtx_handle h, const vggtx_ga_config* cfg, int n_cams, con
       Span sp(h, VGGTX_K_OTHER, 0.0, st);
       VGGTX_HIP(launch_ga_pairs(a, n_pairs, GA_MODE_GRAD, st));
     }
+    VGGTX_HIP(launch_ga_chain(a, n_pairs, st));
     if (loss_out) VGGTX_HIP(launch_ga_loss(w.pair_loss, n_pairs, w.scal, loss_out + it, st));
     VGGTX_HIP(launch_ga_adam(a, n_cams, it + 1, cfg->beta1, cfg->beta2, cfg->eps, st));
   }
