@@ -30,6 +30,10 @@ Parity status by function (what pins each one is listed in tests/test_oracle.py)
   projected-ray constructions, gradient against torch autograd, Adam against
   torch.optim.Adam, histogram weights against a hand-worked example, the
   median rule against numpy.median, pair selection against a camera ring).
+  auc (permutation-equivariant AUC@30): pinned (relative pose against the
+  4x4 matrix inverse, angles against scipy rotation vectors and a closed-form
+  vector pair, a hand-worked three-camera case, the order sensitivity of the
+  conventional form and the order invariance of the both-orders form).
   Agreement of the whole network with a trained VGGT: parity unpinned (no
   trained weights or worked numeric example exist for this path).
 """
@@ -42,3 +46,4 @@ from .fp8 import (e4m3_decode, e4m3_encode, quantize_rows, attention_fp8_emulate
                   logit_factor, E4M3_MAX)
 from .embed import patchify, frame_tokens, embed  # noqa: F401
 from . import ga  # noqa: F401
+from . import auc  # noqa: F401
