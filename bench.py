@@ -255,6 +255,7 @@ def ga_inputs(n_cams, per_pair, seed, dev):
     cameras, 0.5 px noise, 20% outliers; drawn on the device."""
     rng = np.random.default_rng(seed)
     true, init = synth.gen_ga_cameras(rng, n_cams, arc_deg=360.0)
+    init["true_R"], init["true_t"] = true["R"], true["t"]
     pairs = vg.ga_select_pairs(init["R"], 30.0)
     P = len(pairs)
     offsets = [per_pair * m for m in range(P + 1)]
@@ -312,6 +313,15 @@ def bench_ga(args, dev):
     vg.timing_enable(h.h, False)
     lo = lo.cpu().numpy()
     log(f"GA: {args.steps} run(s) in {sec:.3f}s; loss {lo[0]:.4f} -> {lo[-1]:.4f}")
+    tr = [torch.from_numpy(np.ascontiguousarray(init["true_" + k])).to(dev) for k in ("R", "t")]
+    auc0, _ = vg.auc30(h.h, cams[0], cams[1], *tr)
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record()
+    auc1, _ = vg.auc30(h.h, R, t, *tr)
+    a1.record()
+    torch.cuda.synchronize()
+    auc_ms = a0.elapsed_time(a1)
+    log(f"GA: pose AUC@30 (both orders) {auc0.item():.4f} -> {auc1.item():.4f}")
     oth = tm["other"]
     avg_ms = oth["ms"] / max(1, oth["launches"])
     bytes_per_launch = K * 17.0  # float32 x 4 correspondence + uint8 weight bin, per pass
@@ -325,6 +335,8 @@ def bench_ga(args, dev):
         "config": {"workload": f"ga_ring_N{n_cams}_4096perpair", "cameras": n_cams, "pairs": P,
                    "correspondences": K, "iterations": cfg.iterations},
         "loss_first_last": [float(lo[0]), float(lo[-1])],
+        "pose_auc30_initial_aligned": [auc0.item(), auc1.item()],
+        "auc30_ms": auc_ms,
         "roofline": {"kernel": "ga_pair_kernel (residual + gradient pass)", "bound": "hbm", "achieved": achieved,
                      "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0, "traffic": None,
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms, "launches": oth["launches"]},

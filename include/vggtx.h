@@ -315,6 +315,19 @@ vggtx_status vggtx_ga_align(vggtx_handle h, const vggtx_ga_config* cfg, int n_ca
                             double* t_out, double* f_out, float* weights_out, double* loss_out, void* ws,
                             size_t ws_bytes, void* stream);
 
+/* Pose accuracy AUC@30 (the paper's appendix).  For every ordered pair (i, j),
+ * i != j (both_orders != 0, the paper's permutation-equivariant form) or
+ * i < j only (the conventional form): relative poses E_i^-1 E_j =
+ * (R_i^T R_j, R_i^T (t_j - t_i)) of the prediction and the ground truth;
+ * error = max(rotation angle of dR_pred^T dR_gt, angle between dt_pred and
+ * dt_gt (0 if either is zero)) in degrees.  AUC@30 = mean over tau = 1..30
+ * of the fraction of pairs with error < tau.
+ *   R_pred, t_pred, R_gt, t_gt  device float64 [n,3,3], [n,3] (n*n < 2^31)
+ *   counts  device uint32 [31]: errors in [b, b+1) degrees, counts[30] >= 30
+ *   auc     device float64 [1] or null */
+vggtx_status vggtx_auc30(vggtx_handle h, const double* R_pred, const double* t_pred, const double* R_gt,
+                         const double* t_gt, int n, int both_orders, uint32_t* counts, double* auc, void* stream);
+
 /* Kernel timing (tracing).  While enabled, every kernel launch of the classes
  * below is bracketed by a pair of HIP events recorded on its launch stream, and
  * vggtx_timing_read() waits for those events and returns, per class, the summed

@@ -401,7 +401,82 @@ __global__ __launch_bounds__(256) void ga_zero_u32_kernel(uint32_t* x, int n) {
   for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) x[k] = 0u;
 }
 
+// ------------------------------------------------------------------ AUC@30
+// One thread per ordered pair (i, j), i != j (both_orders) or i < j: relative
+// poses E_i^-1 E_j = (R_i^T R_j, R_i^T (t_j - t_i)) of the prediction and the
+// ground truth, error = max(rotation angle of dR_pred^T dR_gt, angle between
+// dt_pred and dt_gt) in degrees, counted in bins [b, b+1) for b < 30 and one
+// bin for 30 or more (integer counts, so the result is exact and order-free).
+__global__ __launch_bounds__(256) void auc30_kernel(const double* Rp, const double* tp, const double* Rg,
+                                                    const double* tg, int n, int both_orders, uint32_t* counts) {
+  __shared__ uint32_t hist[kAucBins];
+  for (int b = threadIdx.x; b < kAucBins; b += 256) hist[b] = 0u;
+  __syncthreads();
+  const int64_t idx = blockIdx.x * 256ll + threadIdx.x;
+  const int64_t nn = (int64_t)n * n;
+  if (idx < nn) {
+    const int i = (int)(idx / n), j = (int)(idx - (int64_t)i * n);
+    if (i != j && (both_orders || i < j)) {
+      double err[2];
+      double dR[2][3][3], dt[2][3];
+      for (int s = 0; s < 2; ++s) {
+        const double* R = s == 0 ? Rp : Rg;
+        const double* t = s == 0 ? tp : tg;
+        const double* Ri = R + 9 * (int64_t)i;
+        const double* Rj = R + 9 * (int64_t)j;
+        for (int r = 0; r < 3; ++r) {
+          for (int c = 0; c < 3; ++c) dR[s][r][c] = Ri[r] * Rj[c] + Ri[3 + r] * Rj[3 + c] + Ri[6 + r] * Rj[6 + c];
+          dt[s][r] = Ri[r] * (t[3 * j] - t[3 * i]) + Ri[3 + r] * (t[3 * j + 1] - t[3 * i + 1]) +
+                     Ri[6 + r] * (t[3 * j + 2] - t[3 * i + 2]);
+        }
+      }
+      // trace(dR_pred^T dR_gt) = sum of the elementwise products
+      double tr = 0.0;
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) tr += dR[0][r][c] * dR[1][r][c];
+      const double kDeg = 57.295779513082320876798;  // 180 / pi
+      err[0] = acos(fmin(1.0, fmax(-1.0, (tr - 1.0) / 2.0))) * kDeg;
+      const double na = sqrt(dt[0][0] * dt[0][0] + dt[0][1] * dt[0][1] + dt[0][2] * dt[0][2]);
+      const double nb = sqrt(dt[1][0] * dt[1][0] + dt[1][1] * dt[1][1] + dt[1][2] * dt[1][2]);
+      err[1] = 0.0;
+      if (na > 0.0 && nb > 0.0) {
+        const double c = (dt[0][0] * dt[1][0] + dt[0][1] * dt[1][1] + dt[0][2] * dt[1][2]) / (na * nb);
+        err[1] = acos(fmin(1.0, fmax(-1.0, c))) * kDeg;
+      }
+      const double e = fmax(err[0], err[1]);
+      const int b = e < (double)(kAucBins - 1) ? (int)floor(e) : kAucBins - 1;
+      atomicAdd(&hist[b], 1u);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kAucBins; b += 256)
+    if (hist[b]) atomicAdd(&counts[b], hist[b]);
+}
+
+// AUC@30 = mean over tau = 1..30 of the fraction of errors below tau.
+__global__ void auc30_finish_kernel(const uint32_t* counts, double* auc) {
+  if (threadIdx.x != 0) return;
+  double total = 0.0;
+  for (int b = 0; b < kAucBins; ++b) total += (double)counts[b];
+  double below = 0.0, s = 0.0;
+  for (int tau = 1; tau < kAucBins; ++tau) {
+    below += (double)counts[tau - 1];
+    s += total > 0.0 ? below / total : 0.0;
+  }
+  *auc = s / (kAucBins - 1);
+}
+
 // ------------------------------------------------------------------ launchers
+hipError_t launch_auc30(const double* Rp, const double* tp, const double* Rg, const double* tg, int n, int both_orders,
+                        uint32_t* counts, double* auc, hipStream_t s) {
+  hipLaunchKernelGGL(ga_zero_u32_kernel, dim3(1), dim3(256), 0, s, counts, kAucBins);
+  const int64_t nn = (int64_t)n * n;
+  if (nn > 0)
+    hipLaunchKernelGGL(auc30_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, Rp, tp, Rg, tg, n,
+                       both_orders, counts);
+  if (auc) hipLaunchKernelGGL(auc30_finish_kernel, dim3(1), dim3(64), 0, s, counts, auc);
+  return hipGetLastError();
+}
 static unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 hipError_t launch_ga_init(const double* R0, const double* t0, int n_cams, double* p, double* adam, hipStream_t s) {

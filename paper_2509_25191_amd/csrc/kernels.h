@@ -146,5 +146,8 @@ hipError_t launch_ga_out(const double* p, const double* f0, int n_cams, double* 
                          hipStream_t s);
 hipError_t launch_ga_weights(const uint8_t* bins, const double* table, int64_t n, float* w, hipStream_t s);
 hipError_t launch_ga_zero_u32(uint32_t* x, int n, hipStream_t s);
+constexpr int kAucBins = 31;  // AUC@30 error bins: [b, b+1) degrees for b < 30, then >= 30
+hipError_t launch_auc30(const double* Rp, const double* tp, const double* Rg, const double* tg, int n, int both_orders,
+                        uint32_t* counts, double* auc, hipStream_t s);
 
 }  // namespace vggtx

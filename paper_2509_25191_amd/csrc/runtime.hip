@@ -1104,6 +1104,21 @@ vggtx_status vggtx_ga_align(vggtx_handle h, const vggtx_ga_config* cfg, int n_ca
                  weights_out, loss_out, ws, ws_bytes, stream);
 }
 
+vggtx_status vggtx_auc30(vggtx_handle h, const double* R_pred, const double* t_pred, const double* R_gt,
+                         const double* t_gt, int n, int both_orders, uint32_t* counts, double* auc, void* stream) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  if (n < 0 || (int64_t)n * n >= ((int64_t)1 << 31)) return fail(VGGTX_E_INVALID, "n = %d", n);
+  const void* ptrs[4] = {R_pred, t_pred, R_gt, t_gt};
+  for (int k = 0; k < 4; ++k)
+    if (n > 0 && (!ptrs[k] || (uintptr_t)ptrs[k] % 8)) return fail(VGGTX_E_INVALID, "pose pointer %d null or misaligned", k);
+  if (!counts || (uintptr_t)counts % 4) return fail(VGGTX_E_INVALID, "counts is null or misaligned");
+  if (auc && (uintptr_t)auc % 8) return fail(VGGTX_E_INVALID, "auc misaligned");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+  VGGTX_HIP(launch_auc30(R_pred, t_pred, R_gt, t_gt, n, both_orders, counts, auc, (hipStream_t)stream));
+  return VGGTX_OK;
+}
+
 vggtx_status vggtx_attn_workspace_size(vggtx_handle h, const int32_t* seq_offsets, int n_seq, int H, int D,
                                        vggtx_prec prec, size_t* bytes) {
   if (!h || !bytes) return fail(VGGTX_E_INVALID, "handle / bytes is null");

@@ -18,7 +18,7 @@ __all__ = [
     "aggregate", "aggregate_varlen", "block", "attn_workspace_size", "attn_frame", "attn_global",
     "quantize_fp8", "status_str", "last_error", "BLOCK_FIELDS", "timing_enable", "timing_read", "timing_poll",
     "autotune_workspace_size", "autotune", "EmbedW", "EMBED_FIELDS", "embed_workspace_size", "embed",
-    "GaConfig", "ga_config_default", "ga_select_pairs", "ga_workspace_size", "ga_align",
+    "GaConfig", "ga_config_default", "ga_select_pairs", "ga_workspace_size", "ga_align", "auc30",
     "K_ATTN_GLOBAL", "K_ATTN_FRAME", "K_GEMM", "K_OTHER",
 ]
 
@@ -111,6 +111,7 @@ def load():
         "vggtx_ga_workspace_size": [vp, i32, i32, i64, ctypes.POINTER(sz)],
         "vggtx_ga_align": [vp, ctypes.POINTER(GaConfig), i32, vp, vp, vp, vp, P_i32, i32,
                            ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp, vp, vp, vp, sz, vp],
+        "vggtx_auc30": [vp, vp, vp, vp, vp, i32, i32, vp, vp, vp],
         "vggtx_timing_enable": [vp, i32],
         "vggtx_timing_read": [vp, ctypes.POINTER(Timing), ctypes.POINTER(ctypes.c_int64)],
         "vggtx_timing_poll": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -370,6 +371,17 @@ def ga_align(h, R0: torch.Tensor, t0: torch.Tensor, f0: torch.Tensor, pp: torch.
                                  _ptr(corr), _ptr(R), _ptr(t), _ptr(f), _ptr(w), _ptr(lo), _ptr(ws), ws.numel(),
                                  _stream(stream)))
     return R, t, f, (w[:K] if w is not None else None), lo
+
+
+def auc30(h, R_pred: torch.Tensor, t_pred: torch.Tensor, R_gt: torch.Tensor, t_gt: torch.Tensor,
+          both_orders: bool = True, stream=None):
+    """Pose AUC@30 on the device: returns (auc float64 [1], counts int32-viewed uint32 [31]) device tensors."""
+    dev = R_pred.device
+    counts = torch.empty(31, dtype=torch.int32, device=dev)
+    auc = torch.empty(1, dtype=torch.float64, device=dev)
+    _check(load().vggtx_auc30(h, _ptr(R_pred), _ptr(t_pred), _ptr(R_gt), _ptr(t_gt), R_pred.shape[0],
+                              1 if both_orders else 0, _ptr(counts), _ptr(auc), _stream(stream)))
+    return auc, counts
 
 
 def timing_enable(h, enable: bool = True) -> None:
