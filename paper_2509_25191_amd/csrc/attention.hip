@@ -559,7 +559,9 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
       if (t == 0 || __any(xmax > kLog2Max)) {
         // the first tile sets the maximum; later tiles only raise it
         const float delta = t == 0 ? xmax - kLog2Max : __builtin_fmaxf(xmax - kLog2Max, 0.f);
-        const float alpha = fast_exp2(-delta);
+        // on the first tile l and O are still zero: no rescale (2^-delta may
+        // overflow there when every logit of the tile is very negative)
+        const float alpha = t == 0 ? 0.f : fast_exp2(-delta);
         l_run[qb] *= alpha;
         m_run[qb] += delta;
         const float c = kLog2Max - m_run[qb];

@@ -103,6 +103,33 @@ def test_attn_global_single_key_tails(handle, prec):
     assert e < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3])
+def test_attn_global_first_tile_far_below_max(handle, prec):
+    """The first 128 keys of each sequence (two key tiles, one FP8 scale
+    block) point against every query (logits near -96, i.e. -138 in base 2)
+    and the later keys give ordinary logits: the first tiles' weights vanish
+    against the row maximum found later, with no overflow in the streamed
+    rescale on the way."""
+    H, D = 2, 64
+    offs = [0, 300, 520]
+    rng = np.random.default_rng(41)
+    u = rng.normal(0, 1, (H, 1, D))
+    u /= np.linalg.norm(u, axis=-1, keepdims=True)
+    n = offs[-1]
+    q = 16.0 * u + rng.normal(0, 0.05, (H, n, D))
+    k = rng.normal(0, 0.1, (H, n, D))
+    for a in offs[:-1]:
+        k[:, a:a + 128] = -48.0 * u + rng.normal(0, 0.05, (H, 128, D))
+    v = rng.normal(0, 1, (H, n, D))
+    if prec != vg.F32:
+        q, k, v = (synth.round_bf16(x.astype(np.float32)) for x in (q, k, v))
+    got = _run_global(handle, q, k, v, offs, prec)
+    ref = _oracle_seqs(q, k, v, offs)
+    e = max_abs_rel(got, ref)
+    print(f"first tile far below max prec={prec} max_abs_rel={e:.3e} finite={np.isfinite(got).all()}")
+    assert np.isfinite(got).all() and e < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", [vg.F32, vg.BF16])
 @pytest.mark.parametrize("S,P", [(8, 86), (3, 1374), (5, 1)])
 def test_attn_frame(handle, prec, S, P):
