@@ -2,7 +2,8 @@
 //   EPI_QKV   [q | k | v] = h W_qkv^T + b, written head-major [H, tokens, D]
 //   EPI_RESID x += y W^T + b in place (attention out-projection and second MLP
 //             Linear), optionally copying the new residual into an output slot
-//   EPI_GELU  hidden = GELU(h W_1^T + b_1) with the exact-erf GELU
+//   EPI_GELU  hidden = GELU(h W_1^T + b_1) with the erf GELU (library erff in
+//             float32; Abramowitz & Stegun 7.1.26 where hidden is bfloat16)
 //   EPI_EMBED patch tokens = patches W_patch^T + b + position embedding,
 //             scattered into the token rows behind each frame's special tokens
 // C[M, N] = A[M, K] W[N, K]^T: both operands are K-contiguous ("NT"), which is
@@ -13,6 +14,26 @@
 namespace vggtx {
 
 __device__ __forceinline__ float gelu_erf(float u) { return 0.5f * u * (1.f + erff(u * 0.70710678118654752f)); }
+
+// GELU with erf from Abramowitz & Stegun 7.1.26 (Hastings): for x >= 0,
+// erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^(-x^2),
+// t = 1 / (1 + p x), |error| <= 1.5e-7; odd extension for x < 0.  Branch free
+// (the library erff takes two code paths per element); used where the result
+// is stored in bfloat16, whose rounding (2^-9 relative) dwarfs that error.
+__device__ __forceinline__ float gelu_erf_as(float u) {
+  const float x = u * 0.70710678118654752f;
+  const float ax = __builtin_fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, ax, 1.f));
+  float poly = __builtin_fmaf(1.061405429f, t, -1.453152027f);
+  poly = __builtin_fmaf(poly, t, 1.421413741f);
+  poly = __builtin_fmaf(poly, t, -0.284496736f);
+  poly = __builtin_fmaf(poly, t, 0.254829592f);
+  poly *= t;
+  const float e = __builtin_amdgcn_exp2f(-ax * ax * 1.4426950408889634f);
+  const float erf_ax = __builtin_fmaf(-poly, e, 1.f);
+  const float erf_x = __builtin_copysignf(erf_ax, x);
+  return 0.5f * u * (1.f + erf_x);
+}
 
 template <typename T> __device__ __forceinline__ void st4(T* p, const float v[4]);
 template <> __device__ __forceinline__ void st4<float>(float* p, const float v[4]) {
@@ -54,6 +75,9 @@ __device__ __forceinline__ void epi4(const GemmParams& p, int r, int col, float 
 #pragma unroll
     for (int j = 0; j < 4; ++j) nv[j] = v[j] + ldf(pos + j);
     st4<float>(p.x + (f * p.emb_pd + kEmbedSpecial + i) * p.ldx + col, nv);
+  } else if (sizeof(T) == 2) {
+    float gv[4] = {gelu_erf_as(v[0]), gelu_erf_as(v[1]), gelu_erf_as(v[2]), gelu_erf_as(v[3])};
+    st4<T>((T*)p.hid + (int64_t)r * p.ldh + col, gv);
   } else {
     float gv[4] = {gelu_erf(v[0]), gelu_erf(v[1]), gelu_erf(v[2]), gelu_erf(v[3])};
     st4<T>((T*)p.hid + (int64_t)r * p.ldh + col, gv);
