@@ -12,7 +12,7 @@
 // residual e = |x'^T F x| / |(F x)_{0,1}|, the pixel distance of x' from the
 // epipolar line of x.
 //
-// Kernels (one workgroup per pair streams that pair's correspondences):
+// Kernels (one wave per pair streams that pair's correspondences):
 //   ga_init_kernel   parameters from the initial cameras, Adam state zeroed
 //   ga_pair_kernel   MODE_BINS: residual histogram bin of every correspondence
 //                    (initial cameras) and the global bin counts;
@@ -120,7 +120,12 @@ __device__ __forceinline__ double residual(const M3& F, const f32x4 c, double g[
 #pragma unroll
   for (int r = 0; r < 3; ++r) l[r] = F.a[r][0] * x[0] + F.a[r][1] * x[1] + F.a[r][2];
   const double s = xp[0] * l[0] + xp[1] * l[1] + l[2];
-  const double rn = 1.0 / sqrt(l[0] * l[0] + l[1] * l[1]);
+  // 1/sqrt(n2): hardware estimate refined by two Newton steps
+  // (y <- y (3 - n2 y^2) / 2, each step doubling the correct bits)
+  const double n2 = l[0] * l[0] + l[1] * l[1];
+  double rn = __builtin_amdgcn_rsq(n2);
+  rn = rn * __builtin_fma(-0.5 * n2 * rn, rn, 1.5);
+  rn = rn * __builtin_fma(-0.5 * n2 * rn, rn, 1.5);
   const double e = fabs(s) * rn;
   if (grad) {
     const double sg = s > 0.0 ? rn : (s < 0.0 ? -rn : 0.0);
@@ -176,39 +181,46 @@ __global__ __launch_bounds__(256) void ga_init_kernel(const double* R0, const do
   for (int i = 0; i < 16; ++i) adam[16 * n + i] = 0.0;
 }
 
-// One workgroup (256 threads) per pair.
+// One wave per pair (four pairs per workgroup): the lanes stride over the
+// pair's correspondences, then a fixed butterfly sums the wave's partial sums,
+// so no workgroup barrier is needed outside the histogram pass.
 template <int MODE>
-__global__ __launch_bounds__(256) void ga_pair_kernel(GaParams a) {
-  __shared__ double red[4];
+__global__ __launch_bounds__(256) void ga_pair_kernel(GaParams a, int n_pairs) {
   __shared__ uint32_t hist[kGaBins + 1];
-  const int m = blockIdx.x;
-  const int i = a.pairs[2 * m], j = a.pairs[2 * m + 1];
-  const int64_t k0 = a.offsets[m], k1 = a.offsets[m + 1];
-  M3 F;
-  {
-    const Cam ci = load_cam(a.p, a.f0, a.pp, i);
-    const Cam cj = load_cam(a.p, a.f0, a.pp, j);
-    F = pair_geom(ci, cj).F;
-  }
+  const int lane = threadIdx.x & 63;
+  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const bool live = m < n_pairs;
   const f32x4* corr = (const f32x4*)a.corr;
   if (MODE == GA_MODE_BINS) {
     for (int b = threadIdx.x; b <= kGaBins; b += 256) hist[b] = 0u;
     __syncthreads();
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
-      double g[3];
-      const double e = residual(F, corr[k], g, false);
-      const int b = e < (double)kGaBins / kGaBinsPerPixel ? (int)floor(e * kGaBinsPerPixel) : kGaBins;
-      a.bins[k] = (uint8_t)b;
-      atomicAdd(&hist[b], 1u);
+    if (live) {
+      const Cam ci = load_cam(a.p, a.f0, a.pp, a.pairs[2 * m]);
+      const Cam cj = load_cam(a.p, a.f0, a.pp, a.pairs[2 * m + 1]);
+      const M3 F = pair_geom(ci, cj).F;
+      for (int64_t k = a.offsets[m] + lane; k < a.offsets[m + 1]; k += 64) {
+        double g[3];
+        const double e = residual(F, corr[k], g, false);
+        const int b = e < (double)kGaBins / kGaBinsPerPixel ? (int)floor(e * kGaBinsPerPixel) : kGaBins;
+        a.bins[k] = (uint8_t)b;
+        atomicAdd(&hist[b], 1u);
+      }
     }
     __syncthreads();
     for (int b = threadIdx.x; b <= kGaBins; b += 256)
       if (hist[b]) atomicAdd(&a.hist[b], hist[b]);
     return;
   }
+  if (!live) return;
+  M3 F;
+  {
+    const Cam ci = load_cam(a.p, a.f0, a.pp, a.pairs[2 * m]);
+    const Cam cj = load_cam(a.p, a.f0, a.pp, a.pairs[2 * m + 1]);
+    F = pair_geom(ci, cj).F;
+  }
   // weighted residual sum and, for MODE_GRAD, sum_k w_k (de_k/dF)
   double acc[10] = {};
-  for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+  for (int64_t k = a.offsets[m] + lane; k < a.offsets[m + 1]; k += 64) {
     const double w = a.table[a.bins[k]];
     const f32x4 c = corr[k];
     double g[3];
@@ -225,19 +237,19 @@ __global__ __launch_bounds__(256) void ga_pair_kernel(GaParams a) {
       }
     }
   }
-  if (MODE == GA_MODE_LOSS) {
-    const double s = block_sum(acc[9], red);
-    if (threadIdx.x == 0) a.pair_loss[m] = s;
-    return;
+  constexpr int NR = MODE == GA_MODE_GRAD ? 10 : 1;
+  const int r0 = MODE == GA_MODE_GRAD ? 0 : 9;
+#pragma unroll
+  for (int r = r0; r < r0 + NR; ++r)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc[r] += __shfl_xor(acc[r], o);
+  if (lane != 0) return;
+  a.pair_loss[m] = acc[9];
+  if (MODE == GA_MODE_GRAD) {
+    double* gf = a.pair_gf + 9 * (int64_t)m;
+#pragma unroll
+    for (int r = 0; r < 9; ++r) gf[r] = acc[r];
   }
-  double tot[10];
-#pragma unroll
-  for (int r = 0; r < 10; ++r) tot[r] = block_sum(acc[r], red);
-  if (threadIdx.x != 0) return;
-  a.pair_loss[m] = tot[9];
-  double* gf = a.pair_gf + 9 * (int64_t)m;
-#pragma unroll
-  for (int r = 0; r < 9; ++r) gf[r] = tot[r];
 }
 
 // One thread per pair: chain rule from dL/dF to the 16 parameters of the two
@@ -486,10 +498,11 @@ hipError_t launch_ga_init(const double* R0, const double* t0, int n_cams, double
 
 hipError_t launch_ga_pairs(const GaParams& a, int n_pairs, int mode, hipStream_t s) {
   if (n_pairs <= 0) return hipSuccess;
+  const dim3 grid(cdiv_u(n_pairs, 4));
   switch (mode) {
-    case GA_MODE_BINS: hipLaunchKernelGGL(ga_pair_kernel<GA_MODE_BINS>, dim3(n_pairs), dim3(256), 0, s, a); break;
-    case GA_MODE_GRAD: hipLaunchKernelGGL(ga_pair_kernel<GA_MODE_GRAD>, dim3(n_pairs), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL(ga_pair_kernel<GA_MODE_LOSS>, dim3(n_pairs), dim3(256), 0, s, a); break;
+    case GA_MODE_BINS: hipLaunchKernelGGL(ga_pair_kernel<GA_MODE_BINS>, grid, dim3(256), 0, s, a, n_pairs); break;
+    case GA_MODE_GRAD: hipLaunchKernelGGL(ga_pair_kernel<GA_MODE_GRAD>, grid, dim3(256), 0, s, a, n_pairs); break;
+    default: hipLaunchKernelGGL(ga_pair_kernel<GA_MODE_LOSS>, grid, dim3(256), 0, s, a, n_pairs); break;
   }
   return hipGetLastError();
 }
