@@ -856,6 +856,8 @@ vggtx_status ga_impl(vggtx_handle h, const vggtx_ga_config* cfg, int n_cams, con
     if (corr_offsets[m + 1] < corr_offsets[m]) return fail(VGGTX_E_INVALID, "corr_offsets decrease at %d", m);
   }
   const int64_t n_corr = n_pairs > 0 ? corr_offsets[n_pairs] : 0;
+  if (n_corr > (int64_t)UINT32_MAX)  // the residual histogram counts in 32 bits
+    return fail(VGGTX_E_UNSUPPORTED, "%lld correspondences exceed 2^32 - 1", (long long)n_corr);
   const void* dptr[7] = {R0, t0, f0, pp, R_out, t_out, f_out};
   for (int k = 0; k < 7; ++k)
     if (!dptr[k] || (uintptr_t)dptr[k] % 8) return fail(VGGTX_E_INVALID, "camera pointer %d is null or misaligned", k);
