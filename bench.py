@@ -363,6 +363,39 @@ def bench_ga(args, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_heads(args, dev):
+    """Head-input packing of the aggregator output at S frames (4 kept layers,
+    P = 1374, 2C = 2048, bfloat16): bytes moved per second."""
+    S, n_out, C2, gh = args.frames, 4, 2048, 37
+    P = 5 + gh * gh
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(args.seed)
+    feats = torch.empty((n_out, S, P, C2), device=dev, dtype=torch.float32)
+    for l in range(n_out):
+        feats[l].normal_(0, 1, generator=gen)
+    feats = feats.to(torch.bfloat16)
+    out = torch.empty((n_out, S, C2, gh, gh), device=dev, dtype=torch.bfloat16)
+    h = vg.Handle(0, dim=1024, heads=16, mlp_hidden=4096)
+    vg.pack_head_inputs(h.h, feats, gh, gh, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        vg.pack_head_inputs(h.h, feats, gh, gh, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / args.steps
+    moved = 2.0 * n_out * S * (P - 5) * C2 * 2  # read the patch rows once, write them once
+    h.close()
+    print(json.dumps({
+        "metric": "head-input packing GB/s (4 kept layers, S frames, 37x37 patches, 2C=2048, bf16)",
+        "value": moved / sec / 1e9, "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (N(0,1) features)", "config": {"workload": f"head_packing_S{S}", "frames": S},
+        "roofline": {"kernel": "pack_heads_kernel", "bound": "hbm", "achieved": moved / sec / 1e9, "peak": 8000.0,
+                     "unit": "GB/s", "frac": moved / sec / 1e9 / 8000.0, "traffic": None}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -375,9 +408,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the run, copy 2 GiB device to device (calibrates HBM byte counters)")
-    ap.add_argument("--stage", choices=["aggregator", "embed", "ga"], default="aggregator",
+    ap.add_argument("--stage", choices=["aggregator", "embed", "ga", "heads"], default="aggregator",
                     help="aggregator (default): the aggregator forward; embed: the patch-embedding front end; "
-                         "ga: camera global alignment")
+                         "ga: camera global alignment; heads: head-input packing")
     ap.add_argument("--cameras", type=int, default=1000, help="--stage ga: number of cameras")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -392,6 +425,9 @@ def main():
         return
     if args.stage == "ga":
         bench_ga(args, dev)
+        return
+    if args.stage == "heads":
+        bench_heads(args, dev)
         return
     S, P = args.frames, P_TOKENS
     model = synth.ModelConfig()

@@ -250,6 +250,17 @@ vggtx_status vggtx_embed(vggtx_handle h, const float* images, int height, int wi
                          const int32_t* frame_offsets, int n_scenes, const vggtx_embed_w* w,
                          float* tokens, vggtx_prec prec, void* ws, size_t ws_bytes, void* stream);
 
+/* Prediction-head inputs (Sec. 3.2: the heads consume the kept layers'
+ * outputs).  For every kept layer l and frame s: out[l, s, c, y, x] =
+ * feats[l, s, 5 + y * grid_w + x, c], c < 2C: the patch tokens behind the 5
+ * special tokens as a channels-first grid_h x grid_w map.
+ *   feats  device [n_out, S, P, 2C] of `dtype` (the vggtx_aggregate output),
+ *          P = 5 + grid_h * grid_w
+ *   out    device [n_out, S, 2C, grid_h, grid_w] of the same type
+ * n_out * S must not exceed 65535. */
+vggtx_status vggtx_pack_head_inputs(vggtx_handle h, const void* feats, vggtx_dtype dtype, int n_out, int S, int P,
+                                    int grid_h, int grid_w, void* out, void* stream);
+
 /* ---------------------------------------------------------------- global alignment
  * Camera global alignment (Sec. 3.3): refine every camera by minimising the
  * weighted mean epipolar residual of Eq. (epi) over the correspondences of

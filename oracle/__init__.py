@@ -34,6 +34,7 @@ Parity status by function (what pins each one is listed in tests/test_oracle.py)
   4x4 matrix inverse, angles against scipy rotation vectors and a closed-form
   vector pair, a hand-worked three-camera case, the order sensitivity of the
   conventional form and the order invariance of the both-orders form).
+  heads.pack_head_inputs: pinned by an index-by-index loop on a small case.
   Agreement of the whole network with a trained VGGT: parity unpinned (no
   trained weights or worked numeric example exist for this path).
 """
@@ -47,3 +48,4 @@ from .fp8 import (e4m3_decode, e4m3_encode, quantize_rows, attention_fp8_emulate
 from .embed import patchify, frame_tokens, embed  # noqa: F401
 from . import ga  # noqa: F401
 from . import auc  # noqa: F401
+from . import heads  # noqa: F401

@@ -7,7 +7,9 @@
 //   embed_special   class token (+ its position embedding) and register tokens
 //   embed_finish    final LayerNorm of the patch tokens, written as aggregator
 //                   input rows, with the camera / register tokens in front
-// All three are memory-bound elementwise passes over the chunk.
+// All three are memory-bound elementwise passes over the chunk.  The file also
+// holds the head-input packing (pack_heads), the token-to-map layout change on
+// the other side of the aggregator.
 #include <algorithm>
 
 #include "common.h"
@@ -112,6 +114,43 @@ __global__ __launch_bounds__(256) void embed_finish_kernel(const float* x, int P
     const int c = lane + 64 * j;
     o[c] = (v[j] - mean) * rstd * ldf(g + c) + ldf(b + c);
   }
+}
+
+// Head inputs (the prediction heads read the kept layers' patch tokens as
+// channels-first maps): for every (layer, frame) the patch rows [n_patch, C2]
+// behind the special tokens are transposed to [C2, n_patch].  One workgroup
+// per 64-token x 64-channel tile, staged through LDS so that both the reads
+// (along channels) and the writes (along tokens) are coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void pack_heads_kernel(const T* feats, int P, int C2, int n_patch, T* out) {
+  __shared__ T tile[64][64 + 2];
+  const int t0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  const int64_t ls = blockIdx.z;  // layer * S + frame
+  const T* src = feats + (ls * P + kEmbedSpecial) * (int64_t)C2;
+  T* dst = out + ls * (int64_t)C2 * n_patch;
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int r = i >> 6, c = i & 63;
+    const int tok = t0 + r, ch = c0 + c;
+    tile[r][c] = (tok < n_patch && ch < C2) ? src[(int64_t)tok * C2 + ch] : (T)0.f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int c = i >> 6, r = i & 63;
+    const int tok = t0 + r, ch = c0 + c;
+    if (tok < n_patch && ch < C2) dst[(int64_t)ch * n_patch + tok] = tile[r][c];
+  }
+}
+
+hipError_t launch_pack_heads(const void* feats, bool bf16_io, int n_ls, int P, int C2, int n_patch, void* out,
+                             hipStream_t s) {
+  if (n_ls <= 0 || n_patch <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((n_patch + 63) / 64), (unsigned)((C2 + 63) / 64), (unsigned)n_ls);
+  if (bf16_io)
+    hipLaunchKernelGGL(pack_heads_kernel<bf16>, grid, dim3(256), 0, s, (const bf16*)feats, P, C2, n_patch, (bf16*)out);
+  else
+    hipLaunchKernelGGL(pack_heads_kernel<float>, grid, dim3(256), 0, s, (const float*)feats, P, C2, n_patch,
+                       (float*)out);
+  return hipGetLastError();
 }
 
 hipError_t launch_pad_cols(const void* w, void* wp, int rows, int K, int Kp, bool bf16_io, hipStream_t s) {

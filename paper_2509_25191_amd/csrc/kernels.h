@@ -107,6 +107,8 @@ hipError_t launch_patchify(const float* img, int height, int width, int64_t f0, 
                            bool bf16_io, hipStream_t s);
 hipError_t launch_embed_special(const void* pos, const void* cls, const void* reg, float* x, int n_frames, int Pd,
                                 int C, bool bf16_io, hipStream_t s);
+hipError_t launch_pack_heads(const void* feats, bool bf16_io, int n_ls, int P, int C2, int n_patch, void* out,
+                             hipStream_t s);
 hipError_t launch_embed_finish(const float* x, int Pd, const void* g, const void* b, float eps, const void* cam,
                                const void* agg_reg, float* out, int64_t f0, int n_frames, const FirstMask& first,
                                int C, bool bf16_io, hipStream_t s);

@@ -1044,6 +1044,25 @@ vggtx_status vggtx_embed(vggtx_handle h, const float* images, int height, int wi
   return embed_impl(h, images, height, width, frame_offsets, n_scenes, w, tokens, prec, ws, ws_bytes, stream);
 }
 
+vggtx_status vggtx_pack_head_inputs(vggtx_handle h, const void* feats, vggtx_dtype dtype, int n_out, int S, int P,
+                                    int grid_h, int grid_w, void* out, void* stream) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  if (dtype != VGGTX_OUT_F32 && dtype != VGGTX_OUT_BF16) return fail(VGGTX_E_INVALID, "unknown dtype");
+  if (n_out < 0 || S < 0 || grid_h <= 0 || grid_w <= 0 || P != kEmbedSpecial + grid_h * grid_w)
+    return fail(VGGTX_E_INVALID, "P = %d must be 5 + grid_h * grid_w (%d x %d)", P, grid_h, grid_w);
+  if ((int64_t)n_out * S > 65535) return fail(VGGTX_E_UNSUPPORTED, "n_out * S = %lld exceeds 65535", (long long)n_out * S);
+  if ((int64_t)n_out * S == 0) return VGGTX_OK;
+  const size_t el = dtype == VGGTX_OUT_F32 ? 4 : 2;
+  if (!feats || !out || (uintptr_t)feats % el || (uintptr_t)out % el)
+    return fail(VGGTX_E_INVALID, "feats / out null or misaligned");
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+  Span sp(h, VGGTX_K_OTHER, 0.0, (hipStream_t)stream);
+  VGGTX_HIP(launch_pack_heads(feats, dtype == VGGTX_OUT_BF16, n_out * S, P, 2 * h->cfg.dim, grid_h * grid_w, out,
+                              (hipStream_t)stream));
+  return VGGTX_OK;
+}
+
 void vggtx_ga_config_default(vggtx_ga_config* cfg) {
   if (!cfg) return;
   cfg->iterations = 300;

@@ -19,6 +19,7 @@ __all__ = [
     "quantize_fp8", "status_str", "last_error", "BLOCK_FIELDS", "timing_enable", "timing_read", "timing_poll",
     "autotune_workspace_size", "autotune", "EmbedW", "EMBED_FIELDS", "embed_workspace_size", "embed",
     "GaConfig", "ga_config_default", "ga_select_pairs", "ga_workspace_size", "ga_align", "auc30",
+    "pack_head_inputs",
     "K_ATTN_GLOBAL", "K_ATTN_FRAME", "K_GEMM", "K_OTHER",
 ]
 
@@ -112,6 +113,7 @@ def load():
         "vggtx_ga_align": [vp, ctypes.POINTER(GaConfig), i32, vp, vp, vp, vp, P_i32, i32,
                            ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp, vp, vp, vp, sz, vp],
         "vggtx_auc30": [vp, vp, vp, vp, vp, i32, i32, vp, vp, vp],
+        "vggtx_pack_head_inputs": [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp],
         "vggtx_timing_enable": [vp, i32],
         "vggtx_timing_read": [vp, ctypes.POINTER(Timing), ctypes.POINTER(ctypes.c_int64)],
         "vggtx_timing_poll": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -382,6 +384,18 @@ def auc30(h, R_pred: torch.Tensor, t_pred: torch.Tensor, R_gt: torch.Tensor, t_g
     _check(load().vggtx_auc30(h, _ptr(R_pred), _ptr(t_pred), _ptr(R_gt), _ptr(t_gt), R_pred.shape[0],
                               1 if both_orders else 0, _ptr(counts), _ptr(auc), _stream(stream)))
     return auc, counts
+
+
+def pack_head_inputs(h, feats: torch.Tensor, grid_h: int, grid_w: int, out: Optional[torch.Tensor] = None,
+                     stream=None) -> torch.Tensor:
+    """feats [n_out, S, P, 2C] (float32 or bfloat16) -> [n_out, S, 2C, grid_h, grid_w]."""
+    n_out, S, P, C2 = feats.shape
+    if out is None:
+        out = torch.empty((n_out, S, C2, grid_h, grid_w), dtype=feats.dtype, device=feats.device)
+    dt = OUT_F32 if feats.dtype == torch.float32 else OUT_BF16
+    _check(load().vggtx_pack_head_inputs(h, _ptr(feats), dt, n_out, S, P, grid_h, grid_w, _ptr(out),
+                                         _stream(stream)))
+    return out
 
 
 def timing_enable(h, enable: bool = True) -> None:

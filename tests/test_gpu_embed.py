@@ -165,3 +165,23 @@ def test_images_to_features_pipeline(prec, tol):
     print(f"pipeline prec={prec}: frame half {ef:.3e}, global half {eg:.3e}")
     assert ef < tol and eg < tol
     h.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.bfloat16])
+def test_pack_head_inputs_bit_exact(dtype):
+    """Head inputs of the kept layers (patch tokens as channels-first maps)
+    equal the oracle's layout change element for element; one case at the
+    VGGT-L shape (37 x 37 patches, 2C = 2048) and one ragged small case."""
+    from oracle import heads
+    for (n_out, S, gh, gw, C) in ((4, 3, 37, 37, 1024), (2, 5, 3, 7, 256)):
+        P = 5 + gh * gw
+        rng = np.random.default_rng(gh)
+        f = rng.normal(0, 1, (n_out, S, P, 2 * C)).astype(np.float32)
+        if dtype == torch.bfloat16:
+            f = synth.round_bf16(f)
+        h = vg.Handle(0, dim=C, heads=C // 64, mlp_hidden=4 * C)
+        got = vg.pack_head_inputs(h.h, to_dev(f, dtype), gh, gw)
+        torch.cuda.synchronize()
+        ref = heads.pack_head_inputs(f, gh, gw)
+        assert np.array_equal(got.float().cpu().numpy(), ref)
+        h.close()

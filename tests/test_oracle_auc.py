@@ -67,3 +67,18 @@ def test_auc_of_constructed_errors():
     # the conventional metric sees only (0,1), (0,2), (1,2): the same multiset here
     a1, c1 = auc.auc30(Rp, t, R, t, both_orders=False)
     assert c1[0] == 1 and c1[10] == 2 and abs(a1 - 7.0 / 9.0) < 1e-12
+
+
+def test_head_input_packing_by_index():
+    from oracle import heads
+    rng = np.random.default_rng(9)
+    gh, gw, C2 = 3, 4, 6
+    f = rng.normal(0, 1, (2, 3, 5 + gh * gw, C2))
+    out = heads.pack_head_inputs(f, gh, gw)
+    assert out.shape == (2, 3, C2, gh, gw)
+    for l in range(2):
+        for s in range(3):
+            for c in range(C2):
+                for y in range(gh):
+                    for x in range(gw):
+                        assert out[l, s, c, y, x] == f[l, s, 5 + y * gw + x, c]
