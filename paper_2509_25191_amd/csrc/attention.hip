@@ -391,15 +391,30 @@ __global__ __launch_bounds__(256, 1) void attn_f32_kernel(AttnParams p) {
 
 
 // ============================================================== FP8 kernel
-// E4M3 conversion of values known to lie in [0, 448 * (1 + 2^-20)]: the
-// folded probabilities below never exceed r_b <= 448 because the running
-// maximum is exact, so no clamp is needed before the hardware converter.
-// Four in-range floats -> four E4M3 codes in one dword (bytes in argument
-// order).  The first conversion fills the low half (its high half is
-// scratch), the second writes the high half in place.
+// E4M3 conversion without a clamp: the hardware rounds to nearest even, so
+// values up to 464 give 448 and larger ones give the NaN code, which the
+// kernel below uses as its overflow signal.  Four floats -> four E4M3 codes
+// in one dword (bytes in argument order).  The first conversion fills the
+// low half (its high half is scratch), the second writes the high half in
+// place.
 __device__ __forceinline__ int pack_e4m3x4(float e0, float e1, float e2, float e3) {
   const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(e0, e1, __float_as_int(e0), false);
   return __builtin_amdgcn_cvt_pk_fp8_f32(e2, e3, lo, true);
+}
+
+// E4M3 probabilities 2^x of one 32-query x 64-key score block, packed as the
+// B operand of the P V product.
+__device__ __forceinline__ i32x8 probs(const f32x16& a, const f32x16& b) {
+  i32x8 pw;
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) {
+    const f32x16& x = kb ? b : a;
+#pragma unroll
+    for (int i = 0; i < 16; i += 4)
+      pw[(16 * kb + i) >> 2] = pack_e4m3x4(fast_exp2(x[i]), fast_exp2(x[i + 1]), fast_exp2(x[i + 2]),
+                                           fast_exp2(x[i + 3]));
+  }
+  return pw;
 }
 
 // Global attention on OCP E4M3 operands (MFMA 32x32x64 f8f6f4 with E8M0
@@ -408,18 +423,31 @@ __device__ __forceinline__ int pack_e4m3x4(float e0, float e1, float e2, float e
 // quantised after multiplication by log2(e)/sqrt(D), so the scaled MFMA
 // yields base-2 logits directly: the Q- and K-block scales enter as the
 // instruction's E8M0 operands.  The accumulator input of the score MFMA is
-// log2(448) - m (m the running row maximum), so the MFMA result x is already
-// the exponent: p = 2^x <= 448 is the E4M3-ready probability, and the tile
-// needs no per-score multiply-add.  Only when a tile raises the maximum (and
-// on the first tile) are its scores shifted, the accumulator rescaled and the
-// accumulator input updated.
+// log2(448) - m per query row, so the MFMA result x is already the exponent:
+// p = 2^x is the E4M3-ready probability and the tile needs no per-score
+// multiply-add.  m is not the running maximum itself: a rescale places the
+// row maximum kHeadroom binades below 448, and later tiles skip the maximum
+// search altogether.  They convert 2^x against the current m; a score that
+// rose more than kHeadroom (+ log2(464/448)) binades above the placed
+// maximum converts to the NaN code, the row-sum MFMA turns that into a NaN
+// sum, and only then are the tile's scores recomputed from the K tile still
+// in LDS and the exact step taken (maximum, rescale, new m).  The first tile
+// and the partial last tile always take the exact step.  Softmax is
+// shift-invariant, so the result does not depend on m; the headroom costs
+// kHeadroom binades of E4M3 range at the small end (probabilities below
+// 2^-9, the smallest subnormal, flush to zero).
 //
 // The V-block scale s_v(b) / vmax enters the P V MFMA as its E8M0 operand
 // for the V tile, so one PV accumulator serves every key block and
 // O = vmax * sum_j p8_j (s_v(j) / vmax) V8_j / sum_j p8_j.  The row sum is
-// taken from the same rounded p8 values that feed the PV product (one extra
-// MFMA against an all-ones operand), so the output stays a convex
-// combination of value rows whatever the rounding of P.
+// taken from the same rounded p8 values that feed the PV product, so the
+// output stays a convex combination of value rows whatever the rounding of
+// P.  It runs on the 16x16x128 MFMA (half the cycles of a 32x32x64 one) and
+// accumulates in that MFMA's accumulator: read as its B operand, the
+// probability registers are 16 columns whose 4 lane groups (k-groups) hold
+// queries n, n+16, n, n+16; the selector A (rows 4j..4j+3 take the groups
+// of parity j&1, E4M3 1.0 or 0) makes output lane l, which holds rows
+// 4*(l/16)+i, receive the sum for its own query l%32 in all four registers.
 //
 // LDS: Ks[key][d] bytes, 16-byte granules swizzled with lds_swz4(key);
 //      Vs[d][key'] bytes, keys of every 32-key block permuted so that lane
@@ -430,6 +458,10 @@ template <int QB, int NW, int OCC>
 __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
   constexpr int BN = 64, D = kHeadDim, BM = 32 * QB * NW, NT = 64 * NW;
   constexpr float kLog2Max = 8.80735492205760410745f;  // log2(448)
+  // a rescale places the row maximum this many binades below 448, so that
+  // later tiles may raise it by up to a factor 2^kHeadroom without overflow
+  constexpr float kHeadroom = 2.f;
+  constexpr float kPlace = kLog2Max - kHeadroom;
   __shared__ __attribute__((aligned(16))) uint8_t Ks[2][BN * D];
   __shared__ __attribute__((aligned(16))) uint8_t Vs[2][D * BN];
 
@@ -445,8 +477,9 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
   const float vmax = p.vmax[head];
 
   const i32x8 zero8 = {};
-  const int one4 = 0x38383838;  // four E4M3 1.0 codes
-  const i32x8 ones8 = {one4, one4, one4, one4, one4, one4, one4, one4};
+  // row-sum selector (see above)
+  const int sel4 = (((lane >> 2) ^ (lane >> 4)) & 1) ? 0 : 0x38383838;  // E4M3 1.0 codes or 0
+  const i32x8 sel8 = {sel4, sel4, sel4, sel4, sel4, sel4, sel4, sel4};
   i32x8 qf[QB];
   int eq[QB];  // E8M0 code of the query block's scale
 #pragma unroll
@@ -506,14 +539,15 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
 
   f32x16 oacc[QB][2];
   f32x16 cin[QB];  // accumulator input of the score MFMA: log2(448) - m, per query
-  float m_run[QB], l_run[QB];
+  float m_run[QB];
+  f32x4 lacc[QB];  // running row sum, kept in the row-sum MFMA's accumulator (4 equal copies)
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     oacc[qb][0] = f32x16{};
     oacc[qb][1] = f32x16{};
     cin[qb] = f32x16{};
-    m_run[qb] = kLog2Max;  // consistent with cin = 0; the first tile always shifts
-    l_run[qb] = 0.f;
+    m_run[qb] = kLog2Max;  // consistent with cin = 0; the first tile always places m
+    lacc[qb] = f32x4{};
   }
   const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
   gload(0);
@@ -542,45 +576,50 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
       s[qb][1] = mfma_fp8_scaled(kf[1], qf[qb], cin[qb], ki[0], eq[qb]);
     }
     i32x8 vf[2];  // V fragments, read just before the first P V product
-    // Query blocks in turn: the softmax of block qb runs on the vector ALU
-    // while the matrix core still works on the score MFMAs of later blocks or
-    // the P V MFMAs of block qb-1 (scheduling fences keep this order).
-#pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-      if (QB > 1) __builtin_amdgcn_sched_barrier(0);
+    // Exact step: mask, row maximum, rescale when the maximum grew (always on
+    // the first tile), then the probabilities.
+    auto exact_probs = [&](int qb, f32x16& a, f32x16& b) {
       if (MASKED) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
           for (int i = 0; i < 16; ++i)
-            if (kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) s[qb][kb][i] = -INFINITY;
+            if (kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) (kb ? b : a)[i] = -INFINITY;
       }
-      const float xmax = lane_swap_max(max32(s[qb][0], s[qb][1]));
+      const float xmax = lane_swap_max(max32(a, b));
       if (t == 0 || __any(xmax > kLog2Max)) {
-        // the first tile sets the maximum; later tiles only raise it
-        const float delta = t == 0 ? xmax - kLog2Max : __builtin_fmaxf(xmax - kLog2Max, 0.f);
+        // the first tile places the maximum; later tiles move it only for
+        // rows that would exceed 448
+        const float delta = t == 0 ? xmax - kPlace : (xmax > kLog2Max ? xmax - kPlace : 0.f);
         // on the first tile l and O are still zero: no rescale (2^-delta may
         // overflow there when every logit of the tile is very negative)
         const float alpha = t == 0 ? 0.f : fast_exp2(-delta);
-        l_run[qb] *= alpha;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lacc[qb][i] *= alpha;
         m_run[qb] += delta;
         const float c = kLog2Max - m_run[qb];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           oacc[qb][0][i] *= alpha;
           oacc[qb][1][i] *= alpha;
-          s[qb][0][i] -= delta;
-          s[qb][1][i] -= delta;
+          a[i] -= delta;
+          b[i] -= delta;
           cin[qb][i] = c;
         }
       }
-      i32x8 pw;
+      return probs(a, b);
+    };
+    // Query blocks in turn: the softmax of block qb runs on the vector ALU
+    // while the matrix core still works on the score MFMAs of later blocks or
+    // the P V MFMAs of block qb-1 (scheduling fences keep this order).
 #pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-        for (int i = 0; i < 16; i += 4)
-          pw[(16 * kb + i) >> 2] = pack_e4m3x4(fast_exp2(s[qb][kb][i]), fast_exp2(s[qb][kb][i + 1]),
-                                               fast_exp2(s[qb][kb][i + 2]), fast_exp2(s[qb][kb][i + 3]));
+    for (int qb = 0; qb < QB; ++qb) {
+      if (QB > 1) __builtin_amdgcn_sched_barrier(0);
+      // full tiles after the first: probabilities against the current m,
+      // the exact step only when the row sum reports an overflow
+      const bool exact = MASKED || t == 0;
+      i32x8 pw = exact ? exact_probs(qb, s[qb][0], s[qb][1]) : probs(s[qb][0], s[qb][1]);
+      f32x4 lsum = mfma_fp8_16(sel8, pw, lacc[qb]);
       if (qb == 0) {
 #pragma unroll
         for (int db = 0; db < 2; ++db) {
@@ -590,11 +629,25 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
           vf[db] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
         }
       }
+      // a NaN code makes the sum NaN; tested on the bits, not with a float
+      // compare (this file is built without NaN semantics)
+      if (!exact && __any((__float_as_uint(lsum[0]) & 0x7fffffffu) >= 0x7f800000u)) {
+        f32x16 r[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+          const int rr = kb * 32 + r32, sw = lds_swz4(rr);
+          const i32x4 lo = *(const volatile i32x4*)&Ks[buf][rr * D + (((2 * g) ^ sw) * 16)];
+          const i32x4 hi = *(const volatile i32x4*)&Ks[buf][rr * D + (((2 * g + 1) ^ sw) * 16)];
+          const i32x8 k8 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+          r[kb] = mfma_fp8_scaled(k8, qf[qb], cin[qb], ki[0], eq[qb]);
+        }
+        pw = exact_probs(qb, r[0], r[1]);
+        lsum = mfma_fp8_16(sel8, pw, lacc[qb]);
+      }
       if (QB > 1) __builtin_amdgcn_sched_barrier(0);
-      const f32x16 lsum = mfma_fp8(ones8, pw, f32x16{});
       oacc[qb][0] = mfma_fp8_scaled(vf[0], pw, oacc[qb][0], ki[1], 127);
       oacc[qb][1] = mfma_fp8_scaled(vf[1], pw, oacc[qb][1], ki[1], 127);
-      l_run[qb] += lsum[0];
+      lacc[qb] = lsum;
     }
     if (QB > 1) __builtin_amdgcn_sched_barrier(0);
     if (t + 1 < ntiles) {
@@ -608,7 +661,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
   if (ragged) tile(ntiles - 1, std::true_type{});
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
-    const float inv = vmax / l_run[qb];
+    const float inv = vmax / lacc[qb][0];
     const int qrow = it.q0 + (wave * QB + qb) * 32 + r32;
     if (qrow < it.s1) {
 #pragma unroll

@@ -130,6 +130,55 @@ def test_attn_global_first_tile_far_below_max(handle, prec):
     assert np.isfinite(got).all() and e < TOL[prec]
 
 
+def _e4m3_rounded(x, offs, pre=None):
+    """x [H, n, D] as the FP8 path sees it: E4M3 codes times the power-of-two
+    scale of their 128-row block (blocks start at every sequence start),
+    quantised after multiplication by ``pre`` and divided by it again."""
+    from oracle import fp8
+    st = np.concatenate([np.arange(a, b, 128) for a, b in zip(offs[:-1], offs[1:])])
+    en = np.concatenate([np.minimum(np.arange(a, b, 128) + 128, b) for a, b in zip(offs[:-1], offs[1:])])
+    out = np.empty(x.shape)
+    for h in range(x.shape[0]):
+        codes, sc = fp8.quantize_rows(x[h], st, en, pre)
+        for i, (a, b) in enumerate(zip(st, en)):
+            out[h, a:b] = fp8.e4m3_decode(codes[a:b]) * np.float64(sc[i])
+    return out / np.float64(pre) if pre is not None else out
+
+
+@pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3])
+def test_attn_global_rising_maximum(handle, prec):
+    """Keys that line up with the queries more and more, tile by tile: in one
+    sequence every 64-key tile raises the row maximum by 3 binades (base-2
+    logits), in the other by 1.2, so in FP8 every tile of the first and every
+    other tile of the second overflow the probability placement and take the
+    recompute-and-rescale path.  FP8 is compared with the oracle on the
+    E4M3-rounded Q, K and V, so that only the rounding of the probabilities
+    and the rescaling are measured."""
+    H, D = 2, 64
+    offs = [0, 900, 1500]
+    rng = np.random.default_rng(43)
+    u = rng.normal(0, 1, (H, 1, D))
+    u /= np.linalg.norm(u, axis=-1, keepdims=True)
+    n = offs[-1]
+    q = 8.0 * u + rng.normal(0, 0.05, (H, n, D))
+    k = np.empty((H, n, D))
+    for (a, b), step in zip(zip(offs[:-1], offs[1:]), (3.0, 1.2)):
+        tile = (np.arange(b - a) // 64)[None, :, None]
+        # q.k / sqrt(D) = level in natural units, i.e. step * tile binades
+        k[:, a:b] = (step * np.log(2.0)) * tile * u + rng.normal(0, 0.05, (H, b - a, D))
+    v = rng.normal(0, 1, (H, n, D))
+    if prec != vg.F32:
+        q, k, v = (synth.round_bf16(x.astype(np.float32)) for x in (q, k, v))
+    got = _run_global(handle, q, k, v, offs, prec)
+    if prec == vg.FP8_E4M3:
+        from oracle import fp8
+        q, k, v = _e4m3_rounded(q, offs, fp8.logit_factor(D)), _e4m3_rounded(k, offs), _e4m3_rounded(v, offs)
+    ref = _oracle_seqs(q, k, v, offs)
+    e = max_abs_rel(got, ref)
+    print(f"rising maximum prec={prec} max_abs_rel={e:.3e}")
+    assert np.isfinite(got).all() and e < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", [vg.F32, vg.BF16])
 @pytest.mark.parametrize("S,P", [(8, 86), (3, 1374), (5, 1)])
 def test_attn_frame(handle, prec, S, P):
