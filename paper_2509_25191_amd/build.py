@@ -33,10 +33,14 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found: the vggtx library needs ROCm's hipcc to build")
 
 
-# Per-file additions.  The attention kernels never produce or consume NaN
-# (masked scores are -inf, never NaN), so max() needs no NaN quieting of the
-# MFMA results; infinities stay honoured.
-FILE_FLAGS = {"attention.hip": ["-fno-honor-nans"]}
+# Per-file additions for attention.hip:
+#  * no float operation there sees a NaN (masked scores are -inf; the FP8
+#    kernel's overflow NaN is tested on its bits), so max() needs no NaN
+#    quieting of the MFMA results; infinities stay honoured;
+#  * machine sinking off: it would move the FP8 kernel's MFMAs of the next
+#    query block (and the P V MFMAs of the previous one) below the overflow
+#    branch, out of the exponentials they are scheduled between.
+FILE_FLAGS = {"attention.hip": ["-fno-honor-nans", "-mllvm", "-disable-machine-sink"]}
 
 
 def _compile(src: str) -> str:

@@ -553,10 +553,13 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
   gload(0);
   lstore(0);
   __syncthreads();
-  // One key tile; MASKED is set only for the final, partial tile of a
-  // sequence, so full tiles carry no key-bound checks.
-  auto tile = [&](int t, auto masked) {
-    constexpr bool MASKED = decltype(masked)::value;
+  // One key tile.  MASKED is set only for the final, partial tile of a
+  // sequence, so full tiles carry no key-bound checks; FIRST only for the
+  // first tile.  Both take the exact step on every query block, the other
+  // tiles the overflow-checked one.
+  auto tile = [&](int t, auto masked, auto first) {
+    constexpr bool MASKED = decltype(masked)::value, FIRST = decltype(first)::value;
+    constexpr bool EXACT = MASKED || FIRST;
     const int kt = it.s0 + t * BN, buf = t & 1;
     if (t + 1 < ntiles) gload(t + 1);
     i32x8 kf[2];
@@ -570,12 +573,16 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
     // key-block E8M0 codes: K scale, V scale relative to vmax
     const i32x2 ki = KI[(kt - it.s0) / kQuantRows];
     f32x16 s[QB][2];
-#pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
+    i32x8 pw[QB];
+    i32x8 vf[2];  // V fragments, read during the first query block
+    auto score = [&](int qb) {
       s[qb][0] = mfma_fp8_scaled(kf[0], qf[qb], cin[qb], ki[0], eq[qb]);
       s[qb][1] = mfma_fp8_scaled(kf[1], qf[qb], cin[qb], ki[0], eq[qb]);
-    }
-    i32x8 vf[2];  // V fragments, read just before the first P V product
+    };
+    auto pv = [&](int qb) {
+      oacc[qb][0] = mfma_fp8_scaled(vf[0], pw[qb], oacc[qb][0], ki[1], 127);
+      oacc[qb][1] = mfma_fp8_scaled(vf[1], pw[qb], oacc[qb][1], ki[1], 127);
+    };
     // Exact step: mask, row maximum, rescale when the maximum grew (always on
     // the first tile), then the probabilities.
     auto exact_probs = [&](int qb, f32x16& a, f32x16& b) {
@@ -587,13 +594,13 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
             if (kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) (kb ? b : a)[i] = -INFINITY;
       }
       const float xmax = lane_swap_max(max32(a, b));
-      if (t == 0 || __any(xmax > kLog2Max)) {
+      if (FIRST || __any(xmax > kLog2Max)) {
         // the first tile places the maximum; later tiles move it only for
         // rows that would exceed 448
-        const float delta = t == 0 ? xmax - kPlace : (xmax > kLog2Max ? xmax - kPlace : 0.f);
+        const float delta = FIRST ? xmax - kPlace : (xmax > kLog2Max ? xmax - kPlace : 0.f);
         // on the first tile l and O are still zero: no rescale (2^-delta may
         // overflow there when every logit of the tile is very negative)
-        const float alpha = t == 0 ? 0.f : fast_exp2(-delta);
+        const float alpha = FIRST ? 0.f : fast_exp2(-delta);
 #pragma unroll
         for (int i = 0; i < 4; ++i) lacc[qb][i] *= alpha;
         m_run[qb] += delta;
@@ -609,17 +616,24 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
       }
       return probs(a, b);
     };
-    // Query blocks in turn: the softmax of block qb runs on the vector ALU
-    // while the matrix core still works on the score MFMAs of later blocks or
-    // the P V MFMAs of block qb-1 (scheduling fences keep this order).
+    // Query blocks in turn.  While the vector ALU runs the exponentials of
+    // block qb, the matrix core gets the score MFMAs of block qb+1 and the
+    // P V MFMAs of block qb-1, issued between the exponentials (scheduling
+    // groups), so that one wave keeps both units busy.
+    score(0);
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-      if (QB > 1) __builtin_amdgcn_sched_barrier(0);
-      // full tiles after the first: probabilities against the current m,
-      // the exact step only when the row sum reports an overflow
-      const bool exact = MASKED || t == 0;
-      i32x8 pw = exact ? exact_probs(qb, s[qb][0], s[qb][1]) : probs(s[qb][0], s[qb][1]);
-      f32x4 lsum = mfma_fp8_16(sel8, pw, lacc[qb]);
+      __builtin_amdgcn_sched_barrier(0);
+      if (qb + 1 < QB) score(qb + 1);
+      if (qb >= 1) pv(qb - 1);
+      pw[qb] = EXACT ? exact_probs(qb, s[qb][0], s[qb][1]) : probs(s[qb][0], s[qb][1]);
+      if (!EXACT && QB > 1) {
+        __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);  // VALU
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 12, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      }
+      f32x4 lsum = mfma_fp8_16(sel8, pw[qb], lacc[qb]);
       if (qb == 0) {
 #pragma unroll
         for (int db = 0; db < 2; ++db) {
@@ -629,9 +643,11 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
           vf[db] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
         }
       }
-      // a NaN code makes the sum NaN; tested on the bits, not with a float
-      // compare (this file is built without NaN semantics)
-      if (!exact && __any((__float_as_uint(lsum[0]) & 0x7fffffffu) >= 0x7f800000u)) {
+      // full tiles after the first: probabilities against the current m; a
+      // NaN code makes the row sum NaN (tested on the bits, not with a float
+      // compare: this file is built without NaN semantics), and only then
+      // are the scores recomputed from the K tile in LDS for the exact step
+      if (!EXACT && __any((__float_as_uint(lsum[0]) & 0x7fffffffu) >= 0x7f800000u)) {
         f32x16 r[2];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
@@ -641,15 +657,14 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
           const i32x8 k8 = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
           r[kb] = mfma_fp8_scaled(k8, qf[qb], cin[qb], ki[0], eq[qb]);
         }
-        pw = exact_probs(qb, r[0], r[1]);
-        lsum = mfma_fp8_16(sel8, pw, lacc[qb]);
+        pw[qb] = exact_probs(qb, r[0], r[1]);
+        lsum = mfma_fp8_16(sel8, pw[qb], lacc[qb]);
       }
-      if (QB > 1) __builtin_amdgcn_sched_barrier(0);
-      oacc[qb][0] = mfma_fp8_scaled(vf[0], pw, oacc[qb][0], ki[1], 127);
-      oacc[qb][1] = mfma_fp8_scaled(vf[1], pw, oacc[qb][1], ki[1], 127);
       lacc[qb] = lsum;
     }
-    if (QB > 1) __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_sched_barrier(0);
+    pv(QB - 1);
+    __builtin_amdgcn_sched_barrier(0);
     if (t + 1 < ntiles) {
       lstore(buf ^ 1);
       __syncthreads();
@@ -657,8 +672,14 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
   };
   const bool ragged = (it.s1 - it.s0) % BN != 0;
   const int nfull = ntiles - (ragged ? 1 : 0);
-  for (int t = 0; t < nfull; ++t) tile(t, std::false_type{});
-  if (ragged) tile(ntiles - 1, std::true_type{});
+  if (nfull > 0) tile(0, std::false_type{}, std::true_type{});
+  for (int t = 1; t < nfull; ++t) tile(t, std::false_type{}, std::false_type{});
+  if (ragged) {
+    if (ntiles == 1)
+      tile(0, std::true_type{}, std::true_type{});
+    else
+      tile(ntiles - 1, std::true_type{}, std::false_type{});
+  }
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     const float inv = vmax / lacc[qb][0];
