@@ -255,7 +255,7 @@ vggtx_status vggtx_embed(vggtx_handle h, const float* images, int height, int wi
  * feats[l, s, 5 + y * grid_w + x, c], c < 2C: the patch tokens behind the 5
  * special tokens as a channels-first grid_h x grid_w map.
  *   feats  device [n_out, S, P, 2C] of `dtype` (the vggtx_aggregate output),
- *          P = 5 + grid_h * grid_w
+ *          P = 5 + grid_h * grid_w, 16-byte aligned
  *   out    device [n_out, S, 2C, grid_h, grid_w] of the same type
  * n_out * S must not exceed 65535. */
 vggtx_status vggtx_pack_head_inputs(vggtx_handle h, const void* feats, vggtx_dtype dtype, int n_out, int S, int P,

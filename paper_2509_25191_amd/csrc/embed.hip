@@ -119,32 +119,39 @@ __global__ __launch_bounds__(256) void embed_finish_kernel(const float* x, int P
 // Head inputs (the prediction heads read the kept layers' patch tokens as
 // channels-first maps): for every (layer, frame) the patch rows [n_patch, C2]
 // behind the special tokens are transposed to [C2, n_patch].  One workgroup
-// per 64-token x 64-channel tile, staged through LDS so that both the reads
-// (along channels) and the writes (along tokens) are coalesced.
+// per 256-token x 32-channel tile: every token's 32 channels are one full
+// 64-byte segment (bf16), read with 16-byte loads, and every output row
+// receives 256 contiguous tokens, so that only the two ends of each run are
+// partial lines.  The tile is transposed in LDS (channel-major).
 template <typename T>
 __global__ __launch_bounds__(256) void pack_heads_kernel(const T* feats, int P, int C2, int n_patch, T* out) {
-  __shared__ T tile[64][64 + 2];
-  const int t0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+  constexpr int TT = 256, TC = 32, VEC = 16 / sizeof(T), GPR = TC / VEC;  // granules per token row
+  __shared__ T tile[TC][TT + 2];
+  const int t0 = blockIdx.x * TT, c0 = blockIdx.y * TC;
   const int64_t ls = blockIdx.z;  // layer * S + frame
-  const T* src = feats + (ls * P + kEmbedSpecial) * (int64_t)C2;
+  const T* src = feats + (ls * P + kEmbedSpecial) * (int64_t)C2 + c0;
   T* dst = out + ls * (int64_t)C2 * n_patch;
-  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-    const int r = i >> 6, c = i & 63;
-    const int tok = t0 + r, ch = c0 + c;
-    tile[r][c] = (tok < n_patch && ch < C2) ? src[(int64_t)tok * C2 + ch] : (T)0.f;
+  typedef __attribute__((__vector_size__(16))) T vec_t;
+  for (int g = threadIdx.x; g < TT * GPR; g += 256) {
+    const int r = g / GPR, v = g % GPR;
+    vec_t x = {};
+    if (t0 + r < n_patch) x = *(const vec_t*)(src + (int64_t)(t0 + r) * C2 + v * VEC);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) tile[v * VEC + j][r] = x[j];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-    const int c = i >> 6, r = i & 63;
-    const int tok = t0 + r, ch = c0 + c;
-    if (tok < n_patch && ch < C2) dst[(int64_t)ch * n_patch + tok] = tile[r][c];
+  const int nt = min(TT, n_patch - t0);
+  for (int i = threadIdx.x; i < TC * TT; i += 256) {
+    const int c = i / TT, r = i % TT;
+    if (r < nt) dst[(int64_t)(c0 + c) * n_patch + t0 + r] = tile[c][r];
   }
 }
 
 hipError_t launch_pack_heads(const void* feats, bool bf16_io, int n_ls, int P, int C2, int n_patch, void* out,
                              hipStream_t s) {
   if (n_ls <= 0 || n_patch <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((n_patch + 63) / 64), (unsigned)((C2 + 63) / 64), (unsigned)n_ls);
+  // C2 is a multiple of 32 (2 x a multiple of the 64-wide head size)
+  const dim3 grid((unsigned)((n_patch + 255) / 256), (unsigned)(C2 / 32), (unsigned)n_ls);
   if (bf16_io)
     hipLaunchKernelGGL(pack_heads_kernel<bf16>, grid, dim3(256), 0, s, (const bf16*)feats, P, C2, n_patch, (bf16*)out);
   else

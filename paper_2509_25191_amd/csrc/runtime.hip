@@ -1053,8 +1053,8 @@ vggtx_status vggtx_pack_head_inputs(vggtx_handle h, const void* feats, vggtx_dty
   if ((int64_t)n_out * S > 65535) return fail(VGGTX_E_UNSUPPORTED, "n_out * S = %lld exceeds 65535", (long long)n_out * S);
   if ((int64_t)n_out * S == 0) return VGGTX_OK;
   const size_t el = dtype == VGGTX_OUT_F32 ? 4 : 2;
-  if (!feats || !out || (uintptr_t)feats % el || (uintptr_t)out % el)
-    return fail(VGGTX_E_INVALID, "feats / out null or misaligned");
+  if (!feats || !out || (uintptr_t)feats % 16 || (uintptr_t)out % el)
+    return fail(VGGTX_E_INVALID, "feats / out null or misaligned (feats needs 16-byte alignment)");
   DeviceGuard dg(h->device);
   if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
   Span sp(h, VGGTX_K_OTHER, 0.0, (hipStream_t)stream);

@@ -185,3 +185,20 @@ def test_pack_head_inputs_bit_exact(dtype):
         ref = heads.pack_head_inputs(f, gh, gw)
         assert np.array_equal(got.float().cpu().numpy(), ref)
         h.close()
+
+
+def test_pack_head_inputs_rejects_misaligned_features():
+    """The packing reads 16-byte granules: a feature pointer off a 16-byte
+    boundary is refused before any launch and the output is left alone."""
+    C, gh, gw = 256, 3, 7
+    P = 5 + gh * gw
+    h = vg.Handle(0, dim=C, heads=C // 64, mlp_hidden=4 * C)
+    base = torch.zeros(2 * P * 2 * C + 8, dtype=torch.bfloat16, device=DEV)
+    feats = base[1:1 + 2 * P * 2 * C].view(1, 2, P, 2 * C)  # 2 bytes past an aligned start
+    out = torch.full((1, 2, 2 * C, gh, gw), 7.0, dtype=torch.bfloat16, device=DEV)
+    with pytest.raises(vg.VggtxError) as e:
+        vg.pack_head_inputs(h.h, feats, gh, gw, out=out)
+    assert e.value.status == E_INVALID
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all())
+    h.close()
