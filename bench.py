@@ -414,7 +414,7 @@ def main():
     ap.add_argument("--cameras", type=int, default=1000, help="--stage ga: number of cameras")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported by this build "
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
               f"(the multi-GPU sharding of the path is a design, not an implementation).", file=sys.stderr)
         sys.exit(2)
 
