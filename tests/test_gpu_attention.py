@@ -311,3 +311,43 @@ def test_autotune_picks_a_variant_and_caches_it(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     assert max_abs_rel(o.float().cpu().numpy().transpose(1, 0, 2), oracle.attention(q, k, v)) < 6e-2
     h.close(); h2.close()
+
+
+def _rising_keys(steps, offs, seed=43, H=2, D=64):
+    rng = np.random.default_rng(seed)
+    n = offs[-1]
+    u = rng.normal(0, 1, (H, 1, D))
+    u /= np.linalg.norm(u, axis=-1, keepdims=True)
+    q = 8.0 * u + rng.normal(0, 0.05, (H, n, D))
+    k = np.empty((H, n, D))
+    for (a, b), step in zip(zip(offs[:-1], offs[1:]), steps):
+        tile = (np.arange(b - a) // 64)[None, :, None]
+        k[:, a:b] = (step * np.log(2.0)) * tile * u + rng.normal(0, 0.05, (H, b - a, D))
+    v = rng.normal(0, 1, (H, n, D))
+    return tuple(synth.round_bf16(x.astype(np.float32)).astype(np.float64) for x in (q, k, v))
+
+
+@pytest.mark.parametrize("case", ["R0", "R1", "R2", "varlen", "rising"])
+def test_attn_global_fp8_matches_streamed_emulation(handle, case):
+    """FP8 global attention against the oracle's emulation of its own
+    arithmetic (E4M3 Q, K, V with power-of-two block scales, probabilities
+    placed tile by tile with two binades of headroom and the overflow
+    fallback), at the FP8 gate: this also gates the large-logit regimes,
+    where the error against the float64 definition is the format's own."""
+    if case in ("R0", "R1", "R2"):
+        q, k, v = _qkv(4, 8 * 86, 64, case, seed=1, frames=8)
+        offs = [0, 8 * 86]
+    elif case == "varlen":
+        q, k, v = _qkv(4, 845, 64, "R1", seed=2)
+        offs = [0, 200, 201, 201, 718, 845]
+    else:
+        offs = [0, 900, 1500]
+        q, k, v = _rising_keys((3.0, 1.2), offs)
+    got = _run_global(handle, q, k, v, offs, vg.FP8_E4M3)
+    emu = np.zeros(q.shape)
+    for a, b in zip(offs[:-1], offs[1:]):
+        if b > a:
+            emu[:, a:b] = oracle.attention_fp8_streamed(q[:, a:b], k[:, a:b], v[:, a:b])[0]
+    e = max_abs_rel(got, emu)
+    print(f"fp8 vs streamed emulation {case}: max_abs_rel={e:.3e}")
+    assert e < TOL[vg.FP8_E4M3]
