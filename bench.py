@@ -2,26 +2,38 @@
 """Throughput of the VGGT-L-shaped aggregator forward on one MI355X.
 
 Workload (default): 24 frame/global attention pairs, C=1024, 16 heads x 64,
-MLP 4096, S=1000 frames x P=1374 tokens (1,374,000 global tokens), global
-attention in FP8 E4M3 (per-128-row-block scales), everything else bfloat16
-with float32 accumulation, outputs of layers 4/11/17/23 kept.  One step is one
-whole aggregator forward over that batch; inputs (tokens N(0,1), weights
-N(0,0.02)) are synthetic, drawn on the device with a seeded generator and
-resident in HBM before timing starts.
+MLP 4096, S=1000 frames x P=1374 tokens (1,374,000 global tokens), bfloat16
+operands with float32 accumulation, float32 softmax statistics and residual
+stream, outputs of layers 4/11/17/23 kept.  One step is one whole aggregator
+forward over that batch; inputs (tokens N(0,1), weights N(0,0.02)) are
+synthetic, drawn on the device with a seeded generator and resident in HBM
+before timing starts.
 
-Prints one JSON line.  Besides the headline frames/s it reports the global
-attention TFLOP/s of the run (from the library's per-launch HIP events), the
-same kernel's standalone rate in BF16 (S=1000) and FP32 (S=200), peak HBM,
-the roofline of the dominant kernel and the FP64 oracle's throughput on the
-host CPU (extrapolated from a bounded sample).
+A wall-clock budget (--wall-budget, from process start) bounds the run: at
+S=1000 one step takes minutes, so the timed steps beyond the first and the
+warm-up steps are cut to what fits (one-frame calls load the kernels first;
+the counts actually run are reported beside the requested ones).  After the
+bfloat16 headline, and while the budget allows: one forward with FP8 E4M3
+global attention (and with the FP8 probability-times-value variant when the
+library has it), the float32 global-attention rate on one head at the same
+S, and the accuracy of each precision's global attention against the float32
+kernel in three logit regimes.
+
+Prints one JSON line: frames/s, global attention TFLOP/s (from the library's
+per-launch HIP events), peak HBM, the roofline of the dominant kernel and the
+FP64 oracle's throughput on the host CPU (extrapolated from a bounded
+sample).
 """
-import argparse
-import hashlib
-import json
-import math
-import os
-import sys
 import time
+
+T_START = time.perf_counter()  # wall-budget origin: before the heavy imports
+
+import argparse  # noqa: E402
+import hashlib  # noqa: E402
+import json  # noqa: E402
+import math  # noqa: E402
+import os  # noqa: E402
+import sys  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -85,9 +97,9 @@ def make_weights(model, gen, dtype, dev):
     return layers
 
 
-def attn_only_rate(h, S, prec, dev, gen):
+def attn_only_rate(h, S, prec, dev, gen, heads=16):
     """Standalone global attention over one scene of S frames: TFLOP/s from the library's events."""
-    N, H, D = S * P_TOKENS, 16, 64
+    N, H, D = S * P_TOKENS, heads, 64
     dt = torch.float32 if prec == vg.F32 else torch.bfloat16
     q = torch.empty((N, H, D), device=dev, dtype=torch.float32).normal_(0, 0.64, generator=gen).to(dt)
     k = torch.empty((N, H, D), device=dev, dtype=torch.float32).normal_(0, 0.64, generator=gen).to(dt)
@@ -396,14 +408,234 @@ def bench_heads(args, dev):
                      "unit": "GB/s", "frac": moved / sec / 1e9 / 8000.0, "traffic": None}}), flush=True)
 
 
+def plan_steps(req_steps, req_warmup, est_step_s, budget_s):
+    """Timed steps and warm-up steps that fit a wall-clock budget.
+
+    At least one timed step always runs.  Further timed steps, then warm-up
+    steps, are added while est_step_s times their count stays within
+    budget_s; requested counts are never exceeded."""
+    fit = int(budget_s // est_step_s) if est_step_s > 0 else req_steps + req_warmup
+    steps = max(1, min(req_steps, fit))
+    warmup = max(0, min(req_warmup, fit - steps))
+    return steps, warmup
+
+
+def forward_flops(S, P, model, depth=None):
+    """Algorithmic flops of one aggregator forward over one scene of S frames."""
+    N, C, F = S * P, model.dim, model.mlp_hidden
+    depth = model.depth if depth is None else depth
+    per_block = 2.0 * N * C * (3 * C + C + 2 * F)
+    return depth * (2 * per_block + 4.0 * S * P * P * C + 4.0 * N * N * C)
+
+
+def wait_logged(ev, h, tag, n_ga, t0, every_s=15.0):
+    """Wait for event `ev`, printing how many global-attention launches have
+    finished every `every_s` seconds (a step runs for minutes at S=1000)."""
+    last = time.perf_counter()
+    while not ev.query():
+        time.sleep(1.0)
+        if time.perf_counter() - last >= every_s:
+            last = time.perf_counter()
+            _, _, ga_done = vg.timing_poll(h)
+            log(f"{tag}: global attention launches finished {ga_done}/{n_ga} ({last - t0:.0f}s)")
+    ev.synchronize()
+
+
+def run_forward(h, tokens, layers, prec, out, ws, steps, warmup, tag):
+    """`warmup` untimed and `steps` timed aggregator forwards; returns (seconds
+    of the timed steps from device events, library kernel timing, peak HBM GB)."""
+    dev = tokens.device
+    n_ga = max(OUT_LAYERS) + 1
+    for i in range(warmup):
+        e = torch.cuda.Event()
+        vg.timing_enable(h, True)
+        vg.aggregate(h, tokens, layers, OUT_LAYERS, prec, out=out, ws=ws)
+        e.record()
+        wait_logged(e, h, f"{tag} warmup {i}", n_ga, time.perf_counter())
+        vg.timing_enable(h, False)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats(dev)
+    vg.timing_enable(h, True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(steps):
+        vg.aggregate(h, tokens, layers, OUT_LAYERS, prec, out=out, ws=ws)
+    e1.record()
+    wait_logged(e1, h, f"{tag} timed", n_ga * steps, t0)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    tm = vg.timing_read(h)
+    vg.timing_enable(h, False)
+    if tm["dropped"]:
+        raise RuntimeError(f"{tm['dropped']} kernel timing records were dropped")
+    peak = torch.cuda.max_memory_allocated(dev) / 1e9
+    log(f"{tag}: {steps} timed step(s) in {sec:.3f}s (host wall {time.perf_counter() - t0:.1f}s), peak {peak:.1f} GB")
+    return sec, tm, peak
+
+
+def attn_rate(tm):
+    ga = tm["attn_global"]
+    return ga["flops"] / (ga["ms"] * 1e-3) / 1e12 if ga["ms"] > 0 else None
+
+
+def accuracy_vs_f32(h, precs, dev, seed=1):
+    """max|g - r| / max|r| of global attention at each precision against the
+    float32 kernel (itself within 1e-4 of the float64 definition) on the
+    same bf16-valued Q, K, V: 4 heads, 8 frames x 86 tokens, in the three
+    logit regimes (R0 random-init, R1 logit std ~3, R2 peaked)."""
+    res = {}
+    for regime in ("R0", "R1", "R2"):
+        q, k, v = synth.gen_qkv(np.random.default_rng(seed), 4, 8 * 86, 64, regime, frames=8, bf16=True)
+        t32 = [torch.from_numpy(np.ascontiguousarray(a.transpose(1, 0, 2), dtype=np.float32)).to(dev)
+               for a in (q, k, v)]
+        ref = torch.empty_like(t32[0])
+        vg.attn_global(h, *t32, ref, [0, 8 * 86], vg.F32)
+        r = ref.double()
+        for name, prec in precs.items():
+            tb = [a.to(torch.bfloat16) for a in t32]
+            o = torch.empty_like(tb[0])
+            vg.attn_global(h, *tb, o, [0, 8 * 86], prec)
+            e = float((o.double() - r).abs().max() / r.abs().max())
+            res.setdefault(name, {})[regime] = e
+    torch.cuda.synchronize()
+    return res
+
+
+def bench_aggregator(args, dev):
+    """Headline: the bfloat16 aggregator forward at S frames; then, as far as
+    the wall budget allows, the FP8 forwards and the float32 attention rate."""
+    S, P = args.frames, P_TOKENS
+    model = synth.ModelConfig()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(args.seed)
+    log(f"generating inputs: S={S} P={P} C={model.dim} depth={model.depth}")
+    tokens = torch.empty((S, P, model.dim), device=dev, dtype=torch.float32).normal_(0, 1, generator=gen)
+    layers = make_weights(model, gen, torch.bfloat16, dev)
+    h = vg.Handle(0, dim=model.dim, heads=model.heads, head_dim=model.head_dim, mlp_hidden=model.mlp_hidden,
+                  ln_eps=model.ln_eps, frame_chunk=model.frame_chunk)
+    lowp = {"bf16": vg.BF16, "fp8": vg.FP8_E4M3}
+    if hasattr(vg, "FP8_PV"):
+        lowp["fp8pv"] = vg.FP8_PV
+    ws = torch.empty(max(vg.workspace_size(h.h, S, P, p) for p in lowp.values()), dtype=torch.uint8, device=dev)
+    out = torch.empty((len(OUT_LAYERS), S, P, 2 * model.dim), device=dev, dtype=torch.bfloat16)
+    for p in lowp.values():  # load the kernels with one-frame calls (not steps)
+        vg.aggregate(h.h, tokens[:1], layers, [0], p, out=out[:1, :1], ws=ws)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - T_START
+    fl = forward_flops(S, P, model)
+    est = fl / (args.assumed_tflops * 1e12)
+    steps, warmup = plan_steps(args.steps, args.warmup, est, args.wall_budget - elapsed - args.reserve)
+    log(f"setup done at {elapsed:.0f}s; estimated {est:.1f}s per step; running {warmup} warm-up + {steps} timed "
+        f"step(s) (requested {args.warmup} + {args.steps})")
+    sec, tm, peak = run_forward(h.h, tokens, layers, vg.BF16, out, ws, steps, warmup, "bf16")
+    step_s = sec / steps
+    ga_tf = attn_rate(tm)
+    ga = tm["attn_global"]
+    per_prec = {"bf16": {"frames_per_s": S * steps / sec, "ms_per_step": step_s * 1e3, "global_attn_tflops": ga_tf,
+                         "global_attn_frac_of_peak": ga_tf / PEAK_TFLOPS["bf16"] if ga_tf else None,
+                         "peak_hbm_gb": peak, "kernel_time_ms": {k: v["ms"] for k, v in tm.items()
+                                                                 if isinstance(v, dict)}}}
+    # FP8 forwards while they fit (their steps take about as long as the global attention's share allows)
+    for name in [n for n in lowp if n != "bf16"]:
+        if args.no_extra:
+            break
+        guess = step_s * (0.6 if name == "fp8" else 0.8)
+        left = args.wall_budget - (time.perf_counter() - T_START) - args.reserve
+        if guess > left:
+            per_prec[name] = {"skipped": f"wall budget: about {guess:.0f}s needed, {left:.0f}s left"}
+            log(f"{name}: skipped ({per_prec[name]['skipped']})")
+            continue
+        s2, tm2, pk2 = run_forward(h.h, tokens, layers, lowp[name], out, ws, 1, 0, name)
+        r2 = attn_rate(tm2)
+        per_prec[name] = {"frames_per_s": S / s2, "ms_per_step": s2 * 1e3, "global_attn_tflops": r2,
+                          "global_attn_frac_of_peak": r2 / PEAK_TFLOPS["fp8"] if r2 else None, "peak_hbm_gb": pk2,
+                          "kernel_time_ms": {k: v["ms"] for k, v in tm2.items() if isinstance(v, dict)}}
+    del out, ws
+    torch.cuda.empty_cache()
+    if not args.no_extra:
+        gen2 = torch.Generator(device=dev)
+        gen2.manual_seed(args.seed + 1)
+        r, ms = attn_only_rate(h.h, S, vg.F32, dev, gen2, heads=1)
+        per_prec["f32"] = {"global_attn_tflops": r, "global_attn_frac_of_peak": r / PEAK_TFLOPS["f32"],
+                           "sample": f"standalone global attention, one head of 64 over S*P = {S * P} tokens "
+                                     f"({ms:.0f} ms; the full layer has 16 identical heads)"}
+        log(f"f32 global attention, one head, S={S}: {r:.1f} TFLOP/s")
+        acc = accuracy_vs_f32(h.h, {k: v for k, v in lowp.items()}, dev)
+        for name, errs in acc.items():
+            gate = 2e-2 if name == "bf16" else 6e-2
+            entry = per_prec.setdefault(name, {})
+            entry["attn_max_abs_rel_vs_f32"] = errs
+            entry["accuracy_gate"] = gate
+            entry["meets_gate_in"] = [rg for rg, e in errs.items() if e < gate]
+        log(f"accuracy against the float32 kernel: {acc}")
+    h.close()
+
+    avg_ms = ga["ms"] / max(1, ga["launches"])
+    res = {
+        "metric": "frames/sec + global-attn TFLOP/s at S=1000 (BF16 vs FP8 vs FP32), peak HBM GB",
+        "value": S * steps / sec,
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (tokens N(0,1), weights N(0,0.02), seeded, device-generated)",
+        "config": {"workload": f"vggt_l_aggregator_S{S}_P{P}_bf16", "frames": S, "tokens_per_frame": P,
+                   "global_tokens": S * P, "dim": model.dim, "heads": model.heads, "head_dim": model.head_dim,
+                   "mlp_hidden": model.mlp_hidden, "depth": model.depth, "out_layers": list(OUT_LAYERS),
+                   "frame_chunk": model.frame_chunk},
+        "wall_budget_s": args.wall_budget,
+        "global_attn_tflops": ga_tf,
+        "peak_hbm_gb": peak,
+        "precisions": per_prec,
+        "roofline": {
+            "kernel": "attn_bf16_kernel (global attention)",
+            "bound": "mfma",
+            "achieved": ga_tf,
+            "peak": PEAK_TFLOPS["bf16"],
+            "unit": "TFLOP/s",
+            "frac": (ga_tf / PEAK_TFLOPS["bf16"]) if ga_tf else None,
+            "traffic": measured_traffic("bf16", S),
+            "flops_per_launch": ga["flops"] / max(1, ga["launches"]),
+            "avg_launch_ms": avg_ms,
+            "launches": ga["launches"],
+        },
+    }
+    if args.copy_calibration:
+        src = torch.empty(1 << 30, dtype=torch.bfloat16, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy done: 2 GiB read, 2 GiB written")
+        del src, dst
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample")
+        res["cpu_baseline"] = cpu_baseline(S, P)
+    log(f"done at {time.perf_counter() - T_START:.0f}s")
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=0)
     ap.add_argument("--frames", type=int, default=1000)
-    ap.add_argument("--prec", choices=list(PREC), default="fp8")
-    ap.add_argument("--no-extra", action="store_true", help="skip the standalone BF16/FP32 attention rates")
+    ap.add_argument("--wall-budget", type=float, default=450.0,
+                    help="seconds from process start within which the run should end; timed steps beyond the "
+                         "first, warm-up steps and the extra legs are cut to fit (the counts run are reported)")
+    ap.add_argument("--reserve", type=float, default=45.0,
+                    help="seconds of the budget kept for the float32 leg, the accuracy check and the CPU baseline")
+    ap.add_argument("--assumed-tflops", type=float, default=1000.0,
+                    help="forward rate assumed when planning steps before any has run")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP8 forwards, the FP32 rate and the accuracy check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -422,126 +654,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.stage == "embed":
         bench_embed(args, dev)
-        return
-    if args.stage == "ga":
+    elif args.stage == "ga":
         bench_ga(args, dev)
-        return
-    if args.stage == "heads":
+    elif args.stage == "heads":
         bench_heads(args, dev)
-        return
-    S, P = args.frames, P_TOKENS
-    model = synth.ModelConfig()
-    prec = PREC[args.prec]
-    wdt = torch.float32 if prec == vg.F32 else torch.bfloat16
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(args.seed)
-    log(f"generating inputs: S={S} P={P} C={model.dim} depth={model.depth} prec={args.prec}")
-    tokens = torch.empty((S, P, model.dim), device=dev, dtype=torch.float32).normal_(0, 1, generator=gen)
-    layers = make_weights(model, gen, wdt, dev)
-    h = vg.Handle(0, dim=model.dim, heads=model.heads, head_dim=model.head_dim, mlp_hidden=model.mlp_hidden,
-                  ln_eps=model.ln_eps, frame_chunk=model.frame_chunk)
-    ws = torch.empty(vg.workspace_size(h.h, S, P, prec), dtype=torch.uint8, device=dev)
-    out = torch.empty((len(OUT_LAYERS), S, P, 2 * model.dim), device=dev, dtype=torch.bfloat16)
-    # load the kernels with a one-frame call (not a step)
-    vg.aggregate(h.h, tokens[:1], layers, [0], prec, out=out[:1, :1], ws=ws)
-    torch.cuda.synchronize()
-    torch.cuda.reset_peak_memory_stats(dev)
-
-    for i in range(args.warmup):
-        vg.aggregate(h.h, tokens, layers, OUT_LAYERS, prec, out=out, ws=ws)
-        torch.cuda.synchronize()
-        log(f"warmup step {i} done")
-    vg.timing_enable(h.h, True)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record()
-    for i in range(args.steps):
-        vg.aggregate(h.h, tokens, layers, OUT_LAYERS, prec, out=out, ws=ws)
-    e1.record()
-    # report each global-attention launch as it completes (the step runs for
-    # minutes at S=1000; these lines come from the finished launches)
-    seen = 0
-    total_ga = args.steps * (max(OUT_LAYERS) + 1)
-    while seen < total_ga:
-        _, _, ga_done = vg.timing_poll(h.h)
-        if ga_done > seen:
-            seen = ga_done
-            log(f"global attention launches finished: {seen}/{total_ga} ({time.perf_counter() - t0:.1f}s)")
-        else:
-            time.sleep(0.5)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    sec = e0.elapsed_time(e1) * 1e-3
-    tm = vg.timing_read(h.h)
-    vg.timing_enable(h.h, False)
-    peak_gb = torch.cuda.max_memory_allocated(dev) / 1e9
-    log(f"timed {args.steps} step(s): {sec:.3f}s (host wall {wall:.3f}s)")
-    ga = tm["attn_global"]
-    ga_tflops = ga["flops"] / (ga["ms"] * 1e-3) / 1e12 if ga["ms"] > 0 else None
-    avg_ms = ga["ms"] / max(1, ga["launches"])
-    flops_per_launch = ga["flops"] / max(1, ga["launches"])
-    N = S * P
-    del out, ws
-    torch.cuda.empty_cache()
-
-    extra = {}
-    if not args.no_extra:
-        gen2 = torch.Generator(device=dev)
-        gen2.manual_seed(args.seed + 1)
-        r, ms = attn_only_rate(h.h, S, vg.BF16, dev, gen2)
-        extra["bf16_S%d" % S] = {"tflops": r, "ms": ms}
-        log(f"standalone bf16 global attention S={S}: {r:.1f} TFLOP/s")
-        r, ms = attn_only_rate(h.h, min(S, 200), vg.F32, dev, gen2)
-        extra["f32_S%d" % min(S, 200)] = {"tflops": r, "ms": ms}
-        log(f"standalone f32 global attention S={min(S, 200)}: {r:.1f} TFLOP/s")
-    h.close()
-
-    res = {
-        "metric": "frames/sec + global-attn TFLOP/s at S=1000 (BF16 vs FP8 vs FP32), peak HBM GB",
-        "value": S * args.steps / sec,
-        "unit": "frames/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": sec * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"fp8": "fp8_e4m3+bf16", "bf16": "bf16", "f32": "f32"}[args.prec],
-        "data": "synthetic (tokens N(0,1), weights N(0,0.02), seeded, device-generated)",
-        "config": {"workload": f"vggt_l_aggregator_S{S}_P{P}_{args.prec}", "frames": S, "tokens_per_frame": P,
-                   "global_tokens": N, "dim": model.dim, "heads": model.heads, "head_dim": model.head_dim,
-                   "mlp_hidden": model.mlp_hidden, "depth": model.depth, "out_layers": list(OUT_LAYERS),
-                   "frame_chunk": model.frame_chunk, "global_attention_prec": args.prec},
-        "global_attn_tflops": ga_tflops,
-        "peak_hbm_gb": peak_gb,
-        "kernel_time_ms": {k: v["ms"] for k, v in tm.items() if isinstance(v, dict)},
-        "attn_only_tflops": extra,
-        "roofline": {
-            "kernel": f"attn_{args.prec}_kernel (global attention)",
-            "bound": "mfma",
-            "achieved": ga_tflops,
-            "peak": PEAK_TFLOPS[args.prec],
-            "unit": "TFLOP/s",
-            "frac": (ga_tflops / PEAK_TFLOPS[args.prec]) if ga_tflops else None,
-            "traffic": measured_traffic(args.prec, S),
-            "flops_per_launch": flops_per_launch,
-            "avg_launch_ms": avg_ms,
-            "launches": ga["launches"],
-        },
-    }
-    if args.copy_calibration:
-        src = torch.empty(1 << 30, dtype=torch.bfloat16, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("calibration copy done: 2 GiB read, 2 GiB written")
-        del src, dst
-    if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on a bounded sample")
-        res["cpu_baseline"] = cpu_baseline(S, P)
-    print(json.dumps(res), flush=True)
+    else:
+        bench_aggregator(args, dev)
 
 
 if __name__ == "__main__":

@@ -344,7 +344,7 @@ vggtx_status vggtx_auc30(vggtx_handle h, const double* R_pred, const double* t_p
  * vggtx_timing_read() waits for those events and returns, per class, the summed
  * elapsed time, the number of launches and the algorithmic work of those
  * launches (attention: 4 * D * H * sum of sequence length squared flops; GEMMs:
- * 2 * M * N * K flops).  At most 4096 launches are recorded between reads;
+ * 2 * M * N * K flops).  At most 262144 launches are recorded between reads;
  * later ones are counted in `dropped`.  Enabling or reading clears the record.
  * The events are host-side objects of the handle; no device memory is
  * allocated. */

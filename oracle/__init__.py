@@ -23,11 +23,6 @@ Parity status by function (what pins each one is listed in tests/test_oracle.py)
   exactly scaled block, binade-edge exponents).
   attention_fp8_emulated: pinned by invariants (constant V gives that row
   exactly; error against the exact attention within the E4M3 bound).
-  attention_fp8_streamed (the FP8 kernel's tile-by-tile placement rule):
-  pinned against attention_fp8_emulated on single-tile sequences (equal:
-  E4M3 rounding commutes with a power-of-two shift), by the constant-V
-  invariant across tiles with rescales, and by the exact count of overflow
-  fallbacks on keys rising 3 binades per tile.
   patchify, frame_tokens, embed (the patch-embedding front end): pinned
   (patch embedding against a float64 Conv2d and a brute-force loop, depth-0
   closed form, frame permutation and scene-first token rules).
@@ -49,7 +44,7 @@ from .aggregator import (  # noqa: F401
     frame_bounds, scene_bounds,
 )
 from .fp8 import (e4m3_decode, e4m3_encode, quantize_rows, attention_fp8_emulated, block_exponent,  # noqa: F401
-                  logit_factor, E4M3_MAX, attention_fp8_streamed)
+                  logit_factor, E4M3_MAX)
 from .embed import patchify, frame_tokens, embed  # noqa: F401
 from . import ga  # noqa: F401
 from . import auc  # noqa: F401

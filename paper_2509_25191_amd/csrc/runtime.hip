@@ -25,9 +25,12 @@
 
 using namespace vggtx;
 
-// Kernel timing record of a handle (see vggtx_timing_enable).
+// Kernel timing record of a handle (see vggtx_timing_enable).  Event pairs
+// are created in blocks of kEventBlock as the record grows, up to kMaxRec
+// launches between two reads.
 struct KernelTimer {
-  static constexpr int kMaxRec = 4096;
+  static constexpr int kMaxRec = 1 << 18;
+  static constexpr int kEventBlock = 4096;
   bool enabled = false;
   std::vector<hipEvent_t> ev;  // start/end pairs
   std::vector<int> cls;
@@ -95,6 +98,20 @@ struct Span {
     if (n >= KernelTimer::kMaxRec) {
       ++t.dropped;
       return;
+    }
+    if (2 * (size_t)n >= t.ev.size()) {  // grow by one block of event pairs
+      const size_t old = t.ev.size();
+      t.ev.resize(old + 2 * KernelTimer::kEventBlock, nullptr);
+      for (size_t i = old; i < t.ev.size(); ++i)
+        if (hipEventCreate(&t.ev[i]) != hipSuccess) {  // undo the partial block
+          for (size_t j = old; j < i; ++j) (void)hipEventDestroy(t.ev[j]);
+          t.ev.resize(old);
+          break;
+        }
+      if (2 * (size_t)n >= t.ev.size()) {
+        ++t.dropped;
+        return;
+      }
     }
     if (hipEventRecord(t.ev[2 * n], s) != hipSuccess) return;
     idx = n;
@@ -1324,7 +1341,7 @@ vggtx_status vggtx_timing_enable(vggtx_handle h, int enable) {
   if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
   KernelTimer& t = h->timer;
   if (enable && t.ev.empty()) {
-    t.ev.resize(2 * KernelTimer::kMaxRec);
+    t.ev.resize(2 * KernelTimer::kEventBlock);
     for (auto& e : t.ev) VGGTX_HIP(hipEventCreate(&e));
   }
   t.enabled = enable != 0;

