@@ -168,6 +168,27 @@ vggtx_status vggtx_attn_global(vggtx_handle h, const void* q, const void* k, con
                                vggtx_layout in_layout, vggtx_layout out_layout, vggtx_prec prec,
                                void* ws, size_t ws_bytes, void* stream);
 
+/* Global attention for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, arguments and results as vggtx_attn_global, with no
+ * workspace argument.  The transposed V (VGGTX_BF16) or the E4M3 codes and
+ * block scales (VGGTX_FP8_E4M3) go to a fixed device array of
+ * VGGTX_NOALLOC_SCRATCH_BYTES bytes inside the library, one per device, held
+ * until the process ends; the call itself allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine) and records no kernel timing.
+ * Returns VGGTX_E_WORKSPACE, having enqueued nothing, when the sequences need
+ * more scratch than that (vggtx_attn_workspace_size gives the need; 64 MiB
+ * hold about 32,000 tokens of 16 heads in BF16 and 21,000 in FP8).  Every
+ * call on one device shares that device's array and overwrites it entirely
+ * before reading it (nothing in it needs to start at zero), so calls that
+ * overlap in time on one device, from any stream or handle, race: the caller
+ * orders them (one stream, or events between streams). */
+#define VGGTX_NOALLOC_SCRATCH_BYTES (64u << 20)
+vggtx_status vggtx_attn_global_noalloc(vggtx_handle h, const void* q, const void* k, const void* v, void* o,
+                                       const int32_t* seq_offsets, int n_seq, int H, int D,
+                                       vggtx_layout in_layout, vggtx_layout out_layout, vggtx_prec prec,
+                                       void* stream);
+
 /* FP8 E4M3 quantiser used by the FP8 global attention.  x: device bfloat16
  * [n_tokens, H, D] with layout `in_layout`.  For every head and every
  * 128-token block of every sequence (blocks start at each sequence start; the

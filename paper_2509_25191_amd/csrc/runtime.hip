@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <cstdlib>
 #include <cmath>
@@ -45,7 +46,16 @@ struct vggtx_ctx {
   KernelTimer timer;
   int bf16_variant;  // BF16 attention kernel variant (index into the BF16 variant table)
   int fp8_variant;   // FP8 attention kernel variant (index into the FP8 variant table)
+  bool timing_off;   // set while an entry point that must not create events runs
 };
+
+// Device scratch of the entry point that allocates nothing
+// (vggtx_attn_global_noalloc): one array per device, loaded with the code
+// object and held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the symbol):
+// vggtx_create looks up its device address once per device, with that device
+// current, and every use goes through that address.
+static __device__ __align__(256) uint8_t scratch[VGGTX_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -85,6 +95,27 @@ struct DeviceGuard {
   }
 };
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device (null until looked up)
+
+// Looks up (once per device) the address of `scratch` on `device`, which must
+// be the current device.
+hipError_t scratch_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
 // Brackets the launches issued during its lifetime with timing events when
 // the handle's timer is enabled.
 struct Span {
@@ -93,7 +124,7 @@ struct Span {
   hipStream_t s;
   Span(vggtx_ctx* ctx, int cls, double flops, hipStream_t st) : c(ctx), s(st) {
     KernelTimer& t = c->timer;
-    if (!t.enabled) return;
+    if (!t.enabled || c->timing_off) return;
     const int n = (int)t.cls.size();
     if (n >= KernelTimer::kMaxRec) {
       ++t.dropped;
@@ -958,9 +989,17 @@ vggtx_status vggtx_create(vggtx_handle* h, int device, const vggtx_config* cfg) 
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(VGGTX_E_NODEVICE, "cannot query device %d", device);
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(VGGTX_E_UNSUPPORTED, "device %d is %s; the kernels are built for gfx950", device, prop.gcnArchName);
+  if (device < kMaxDevices) {
+    DeviceGuard dg(device);
+    if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", device);
+    const hipError_t e = scratch_setup(device);
+    if (e != hipSuccess)
+      return fail(VGGTX_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+  }
   vggtx_ctx* c = new (std::nothrow) vggtx_ctx;
   if (!c) return fail(VGGTX_E_INVALID, "out of host memory");
   c->device = device;
+  c->timing_off = false;
   snprintf(c->arch, sizeof(c->arch), "%s", prop.gcnArchName);
   c->cfg = *cfg;
   // defaults measured on MI355X (VGGT-L shapes); vggtx_autotune can re-pick them
@@ -1185,6 +1224,29 @@ vggtx_status vggtx_attn_global(vggtx_handle h, const void* q, const void* k, con
   VGGTX_TRY(check_offsets(seq_offsets, n_seq, "sequence"));
   const Seqs s = seqs_from_offsets(seq_offsets, n_seq, 1);
   return attn_entry(h, VGGTX_K_ATTN_GLOBAL, q, k, v, o, s, H, D, in_layout, out_layout, prec, ws, ws_bytes, stream);
+}
+
+vggtx_status vggtx_attn_global_noalloc(vggtx_handle h, const void* q, const void* k, const void* v, void* o,
+                                       const int32_t* seq_offsets, int n_seq, int H, int D, vggtx_layout in_layout,
+                                       vggtx_layout out_layout, vggtx_prec prec, void* stream) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  VGGTX_TRY(check_prec(prec));
+  VGGTX_TRY(check_offsets(seq_offsets, n_seq, "sequence"));
+  if (D != kHeadDim) return fail(VGGTX_E_UNSUPPORTED, "head dim %d: only 64 is supported", D);
+  if (H <= 0) return fail(VGGTX_E_INVALID, "H = %d", H);
+  const Seqs s = seqs_from_offsets(seq_offsets, n_seq, 1);
+  const size_t need = carve_attn(H, seq_offsets[n_seq], s.padded_cols(), s.scale_blocks(), prec, nullptr).total;
+  if (need > (size_t)VGGTX_NOALLOC_SCRATCH_BYTES)
+    return fail(VGGTX_E_WORKSPACE, "needs %zu bytes of scratch, the fixed device scratch holds %zu", need,
+                (size_t)VGGTX_NOALLOC_SCRATCH_BYTES);
+  void* ws = h->device < kMaxDevices ? scratch_ptr(h->device) : nullptr;
+  if (!ws) return fail(VGGTX_E_UNSUPPORTED, "no device scratch on device %d", h->device);
+  // timing events are created on demand; this entry point records none
+  h->timing_off = true;
+  const vggtx_status rc = attn_entry(h, VGGTX_K_ATTN_GLOBAL, q, k, v, o, s, H, D, in_layout, out_layout, prec, ws,
+                                     VGGTX_NOALLOC_SCRATCH_BYTES, stream);
+  h->timing_off = false;
+  return rc;
 }
 
 vggtx_status vggtx_quantize_fp8(vggtx_handle h, const void* x, vggtx_layout in_layout, const int32_t* seq_offsets,

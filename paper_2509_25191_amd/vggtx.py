@@ -102,6 +102,7 @@ def load():
         "vggtx_attn_workspace_size": [vp, P_i32, i32, i32, i32, i32, ctypes.POINTER(sz)],
         "vggtx_attn_frame": [vp, vp, vp, vp, vp, i32, i32, i32, i32, Layout, Layout, i32, vp, sz, vp],
         "vggtx_attn_global": [vp, vp, vp, vp, vp, P_i32, i32, i32, i32, Layout, Layout, i32, vp, sz, vp],
+        "vggtx_attn_global_noalloc": [vp, vp, vp, vp, vp, P_i32, i32, i32, i32, Layout, Layout, i32, vp],
         "vggtx_quantize_fp8": [vp, vp, Layout, P_i32, i32, i32, i32, vp, vp, vp],
         "vggtx_autotune_workspace_size": [vp, i32, ctypes.POINTER(sz)],
         "vggtx_autotune": [vp, i32, i32, vp, sz, vp, ctypes.POINTER(i32)],
@@ -265,6 +266,15 @@ def attn_global(h, q, k, v, o, seq_offsets: Sequence[int], prec: int, ws: Option
     _check(load().vggtx_attn_global(h, _ptr(q), _ptr(k), _ptr(v), _ptr(o), _i32_array(seq_offsets),
                                     len(seq_offsets) - 1, H, D, _layout(q), _layout(o), prec, _ptr(ws), ws.numel(),
                                     _stream(stream)))
+    return o
+
+
+def attn_global_noalloc(h, q, k, v, o, seq_offsets: Sequence[int], prec: int, stream=None):
+    """vggtx_attn_global with the library's fixed device scratch (no workspace)."""
+    H, D = q.shape[1], q.shape[2]
+    _check(load().vggtx_attn_global_noalloc(h, _ptr(q), _ptr(k), _ptr(v), _ptr(o), _i32_array(seq_offsets),
+                                            len(seq_offsets) - 1, H, D, _layout(q), _layout(o), prec,
+                                            _stream(stream)))
     return o
 
 
