@@ -69,6 +69,9 @@ typedef struct {
   int mlp_hidden;   /* F; multiple of 128 */
   float ln_eps;     /* LayerNorm epsilon (1e-6 by default) */
   int frame_chunk;  /* frames per chunk for token-local work; results do not depend on it */
+  int tokens_inplace; /* 1: vggtx_aggregate[_varlen] keep the residual stream in the caller's tokens
+                         buffer (which must then be writable; it is overwritten) instead of a copy
+                         in the workspace, whose size shrinks by S*P*C*4 bytes; 0: tokens are read only */
 } vggtx_config;
 
 /* Device pointers of one block's parameters: float32 for VGGTX_F32, bfloat16
@@ -103,7 +106,10 @@ vggtx_status vggtx_destroy(vggtx_handle h);
 vggtx_status vggtx_workspace_size(vggtx_handle h, int total_frames, int P, vggtx_prec prec, size_t* bytes);
 
 /* Aggregator forward over one scene (Sec. 3.2).
- *   tokens     device, float32 [S, P, C] (read only)
+ *   tokens     device, float32 [S, P, C]; read only, unless the handle's
+ *              config sets tokens_inplace: then the forward runs its residual
+ *              stream in this buffer and leaves it holding the last computed
+ *              layer's global-block output
  *   w          host array[depth] of per-layer weight pointers
  *   out_layers host int32 [n_out], strictly increasing, each in [0, depth)
  *   out        device [n_out, S, P, 2C] of `out_dtype`: out[i, s, p, 0:C] is the
@@ -387,7 +393,10 @@ vggtx_status vggtx_timing_enable(vggtx_handle h, int enable);
 vggtx_status vggtx_timing_read(vggtx_handle h, vggtx_timing out[VGGTX_K_COUNT], int64_t* dropped);
 /* Non-blocking progress query: of the launches recorded since the last
  * enable/read, how many have finished (in issue order) and how many of those
- * were global-attention launches.  Does not wait and does not clear. */
+ * were global-attention launches.  Does not wait and does not clear.  Unlike
+ * the other entry points it may be called from a second thread while a call
+ * on the same handle is still enqueueing work (a long forward can block its
+ * caller inside the launch queue). */
 vggtx_status vggtx_timing_poll(vggtx_handle h, int64_t* finished, int64_t* recorded, int64_t* finished_attn_global);
 
 const char* vggtx_status_str(vggtx_status s);

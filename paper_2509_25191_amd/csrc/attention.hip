@@ -755,7 +755,8 @@ __device__ __forceinline__ float exp2i(int e) {
 // exponent field is the OCP E8M0 code of the scale).
 __global__ __launch_bounds__(256) void quant_fp8_kernel(const bf16* x, int64_t x_ts, int64_t x_hs, float pre,
                                                         uint8_t* codes, int64_t c_hs, int64_t c_ds, int transposed,
-                                                        float* scales, int64_t sc_hs, SeqTable seqs) {
+                                                        int64_t out_row0, float* scales, int64_t sc_hs,
+                                                        SeqTable seqs) {
   __shared__ float red[4];
   __shared__ uint8_t T[64][128 + 4];
   const int tid = threadIdx.x, head = blockIdx.y;
@@ -789,7 +790,7 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(const bf16* x, int64_t x
     w[j] = cvt_e4m3x2(v[4 * j] * inv, v[4 * j + 1] * inv) | (cvt_e4m3x2(v[4 * j + 2] * inv, v[4 * j + 3] * inv) << 16);
   if (!transposed) {
     if (valid) {
-      uint8_t* o = codes + head * c_hs + (int64_t)row * kHeadDim + half * 32;
+      uint8_t* o = codes + head * c_hs + (out_row0 + row) * kHeadDim + half * 32;
       const i32x4 a = {(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
       const i32x4 b = {(int)w[4], (int)w[5], (int)w[6], (int)w[7]};
       *(i32x4*)o = a;
@@ -916,10 +917,10 @@ hipError_t launch_v_transpose_bf16(const bf16* v, int64_t v_ts, int64_t v_hs, bf
 }
 
 hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, float pre, uint8_t* codes, int64_t c_hs,
-                            int64_t c_ds, bool transposed, float* scales, int64_t sc_hs, const SeqTable& seqs,
-                            int n_blocks, int H, hipStream_t s) {
+                            int64_t c_ds, bool transposed, int64_t out_row0, float* scales, int64_t sc_hs,
+                            const SeqTable& seqs, int n_blocks, int H, hipStream_t s) {
   hipLaunchKernelGGL(quant_fp8_kernel, dim3(n_blocks, H), dim3(256), 0, s, x, x_ts, x_hs, pre, codes, c_hs, c_ds,
-                     transposed ? 1 : 0, scales, sc_hs, seqs);
+                     transposed ? 1 : 0, out_row0, scales, sc_hs, seqs);
   return hipGetLastError();
 }
 

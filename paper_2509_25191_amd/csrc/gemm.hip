@@ -56,8 +56,11 @@ __device__ __forceinline__ void epi4(const GemmParams& p, int r, int col, float 
   if (EPI == EPI_QKV) {
     const int part = col / p.C, cc = col - part * p.C;
     const int hh = cc / kHeadDim, d = cc - hh * kHeadDim;
-    T* base = (T*)(part == 0 ? p.q : (part == 1 ? p.k : p.v));
-    st4<T>(base + hh * p.qkv_hs + grow * kHeadDim + d, v);
+    if (part == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] *= p.q_scale;
+    }
+    st4<T>((T*)p.qkv[part] + hh * p.qkv_hs[part] + (int64_t)r * kHeadDim + d, v);
   } else if (EPI == EPI_RESID) {
     float* x = p.x + grow * p.ldx + col;
     const f32x4 old = *(const f32x4*)x;
@@ -110,7 +113,9 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = (tid >> 3) + 32 * i, ch = tid & 7;
-      areg[i] = (m0 + r < p.M) ? *(const bf16x8*)(A + (int64_t)(m0 + r) * p.lda + k0 + ch * 8) : zero8;
+      const bf16* a = p.a_hs ? A + (k0 >> 6) * p.a_hs + (int64_t)(m0 + r) * kHeadDim + ch * 8
+                             : A + (int64_t)(m0 + r) * p.lda + k0 + ch * 8;
+      areg[i] = (m0 + r < p.M) ? *(const bf16x8*)a : zero8;
       wreg[i] = *(const bf16x8*)(W + (int64_t)(n0 + r) * p.K + k0 + ch * 8);
     }
   };
@@ -194,7 +199,9 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmParams p) {
   const int lr = tid >> 2, lk = (tid & 3) * 4;
   for (int k0 = 0; k0 < p.K; k0 += BK) {
     f32x4 av = {}, wv;
-    if (m0 + lr < p.M) av = *(const f32x4*)(A + (int64_t)(m0 + lr) * p.lda + k0 + lk);
+    if (m0 + lr < p.M)
+      av = *(const f32x4*)(p.a_hs ? A + (k0 >> 6) * p.a_hs + (int64_t)(m0 + lr) * kHeadDim + (k0 & 63) + lk
+                                  : A + (int64_t)(m0 + lr) * p.lda + k0 + lk);
     wv = *(const f32x4*)(W + (int64_t)(n0 + lr) * p.K + k0 + lk);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {

@@ -54,10 +54,11 @@ hipError_t launch_v_transpose_bf16(const bf16* v, int64_t v_ts, int64_t v_hs, bf
 
 // FP8 quantiser: x [tokens, H, D] bf16, times the float32 factor `pre`, ->
 // codes and per-(head, 128-row block) power-of-two scales.
-// transposed == false: codes [H, tokens, D] (row-major, c_hs = tokens*D)
+// transposed == false: codes [H, tokens, D] (row-major, c_hs = tokens*D);
+//   token t of the table lands in code row out_row0 + t
 // transposed == true:  codes [H, D, padded tokens] like vt above (zero padding).
 hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, float pre, uint8_t* codes, int64_t c_hs,
-                            int64_t c_ds, bool transposed, float* scales, int64_t sc_hs,
+                            int64_t c_ds, bool transposed, int64_t out_row0, float* scales, int64_t sc_hs,
                             const SeqTable& seqs, int n_blocks, int H, hipStream_t s);
 // Per-head max of the V block scales -> vmax[H], then per key block b the
 // E8M0 codes kinfo[h][b] = {E8M0(s_k(b)), E8M0(s_v(b) / vmax[h])}.
@@ -68,13 +69,16 @@ hipError_t launch_scale_max(const float* sk, const float* sv, int64_t sc_hs, int
 enum Epi { EPI_QKV = 0, EPI_RESID = 1, EPI_GELU = 2, EPI_EMBED = 3 };
 
 struct GemmParams {
-  const void* a; int64_t lda;      // A rows (bf16 or f32)
+  const void* a; int64_t lda;      // A rows (bf16 or f32), row-major with leading dimension lda, or
+  int64_t a_hs;                    // when a_hs != 0: head-major, A(m, k) at a[(k / 64) * a_hs + m * 64 + k % 64]
   const void* w;                   // W [N, K] row-major (bf16 or f32)
   const void* bias;                // [N] (bf16 or f32)
   int M, N, K;
   int row0;                        // global token index of A's first row
-  // EPI_QKV: q, k, v [H, n_tokens, D] (bf16 or f32); C = H*D
-  void* q; void* k; void* v; int64_t qkv_hs; int C;
+  // EPI_QKV: part j of [q | k | v] (C = H*D columns each), head h, A's row r,
+  // dimension d goes to qkv[j][h * qkv_hs[j] + r * D + d] (bf16 or f32); the q
+  // part is multiplied by q_scale before it is stored
+  void* qkv[3]; int64_t qkv_hs[3]; int C; float q_scale;
   // EPI_RESID: x[row0 + r, c] += result (float32, leading dim ldx); optional copy to out
   float* x; int64_t ldx;
   void* out; int64_t ldo; int out_f32;

@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <fstream>
+#include <atomic>
 #include <mutex>
 #include <sstream>
 #include <cstdlib>
@@ -26,16 +27,22 @@
 
 using namespace vggtx;
 
-// Kernel timing record of a handle (see vggtx_timing_enable).  Event pairs
-// are created in blocks of kEventBlock as the record grows, up to kMaxRec
-// launches between two reads.
+// Kernel timing record of a handle (see vggtx_timing_enable).  The slot
+// arrays are sized for kMaxRec launches when timing is first enabled and never
+// move afterwards; event pairs are created in blocks of kEventBlock as the
+// record grows.  One thread records (the thread enqueueing work on the
+// handle); `n`, the number of records whose end event has been enqueued, is
+// published last, so vggtx_timing_poll can read the first n slots from
+// another thread without a lock.
 struct KernelTimer {
   static constexpr int kMaxRec = 1 << 18;
   static constexpr int kEventBlock = 4096;
   bool enabled = false;
-  std::vector<hipEvent_t> ev;  // start/end pairs
-  std::vector<int> cls;
-  std::vector<double> flops;
+  std::vector<hipEvent_t> ev;  // start/end pairs, 2 * kMaxRec slots
+  std::vector<int> cls;        // kMaxRec slots
+  std::vector<double> flops;   // kMaxRec slots
+  int created = 0;             // event pairs created so far
+  std::atomic<int> n{0};
   int64_t dropped = 0;
 };
 
@@ -125,32 +132,31 @@ struct Span {
   Span(vggtx_ctx* ctx, int cls, double flops, hipStream_t st) : c(ctx), s(st) {
     KernelTimer& t = c->timer;
     if (!t.enabled || c->timing_off) return;
-    const int n = (int)t.cls.size();
+    const int n = t.n.load(std::memory_order_relaxed);
     if (n >= KernelTimer::kMaxRec) {
       ++t.dropped;
       return;
     }
-    if (2 * (size_t)n >= t.ev.size()) {  // grow by one block of event pairs
-      const size_t old = t.ev.size();
-      t.ev.resize(old + 2 * KernelTimer::kEventBlock, nullptr);
-      for (size_t i = old; i < t.ev.size(); ++i)
+    if (n >= t.created) {  // create the next block of event pairs in place
+      const int end = std::min(KernelTimer::kMaxRec, t.created + KernelTimer::kEventBlock);
+      for (int i = 2 * t.created; i < 2 * end; ++i)
         if (hipEventCreate(&t.ev[i]) != hipSuccess) {  // undo the partial block
-          for (size_t j = old; j < i; ++j) (void)hipEventDestroy(t.ev[j]);
-          t.ev.resize(old);
-          break;
+          for (int j = 2 * t.created; j < i; ++j) (void)hipEventDestroy(t.ev[j]);
+          ++t.dropped;
+          return;
         }
-      if (2 * (size_t)n >= t.ev.size()) {
-        ++t.dropped;
-        return;
-      }
+      t.created = end;
     }
     if (hipEventRecord(t.ev[2 * n], s) != hipSuccess) return;
     idx = n;
-    t.cls.push_back(cls);
-    t.flops.push_back(flops);
+    t.cls[n] = cls;
+    t.flops[n] = flops;
   }
   ~Span() {
-    if (idx >= 0) (void)hipEventRecord(c->timer.ev[2 * idx + 1], s);
+    if (idx < 0) return;
+    KernelTimer& t = c->timer;
+    if (hipEventRecord(t.ev[2 * idx + 1], s) != hipSuccess) return;
+    t.n.store(idx + 1, std::memory_order_release);
   }
 };
 
@@ -238,18 +244,23 @@ std::vector<std::pair<SeqTable, int>> make_tables(const Seqs& s, int rows) {
 }
 
 // -------------------------------------------------------------- workspace
+// Buffers of one forward.  Token-local work (LayerNorm, projections, MLP)
+// runs over row ranges of at most `rows` tokens: whole frames for frame
+// blocks (the frame chunk), scene-aligned pieces for global blocks.  Global
+// attention needs the K and V of every token of a scene at once; everything
+// else lives only for one row range.
 struct Ws {
-  float* x = nullptr;        // residual stream [N, C] f32
-  void* q = nullptr;         // [H, N, D] bf16 (f32 for the F32 path)
-  void* k = nullptr;
-  void* v = nullptr;
-  bf16* vt = nullptr;        // [H, D, Npad] bf16
-  void* o = nullptr;         // [N, C] bf16 / f32
-  void* h = nullptr;         // [R, C] bf16 / f32
-  void* hid = nullptr;       // [R, F] bf16 / f32
+  float* x = nullptr;        // residual stream [N, C] f32 (not carved when the caller's tokens are used in place)
+  void* q = nullptr;         // BF16 / F32: [H, N, D]; FP8: [H, rows, D] staging.  Attention writes O over Q
+  void* k = nullptr;         //   (same shape as q)
+  void* v = nullptr;         // F32: [H, N, D]; BF16 / FP8: [H, rows, D] staging of V before its transposition
+  bf16* vt = nullptr;        // BF16 / FP8: transposed V [H, D, vt_cols] (FP8: frame chunks only)
+  void* o = nullptr;         // FP8: global attention output [H, N, D] bf16
+  void* h = nullptr;         // LayerNorm output [rows, C]
+  void* hid = nullptr;       // MLP hidden [rows, F]
   uint8_t* q8 = nullptr;     // FP8 codes [H, N, D]
   uint8_t* k8 = nullptr;
-  uint8_t* v8t = nullptr;    // [H, D, Npad]
+  uint8_t* v8t = nullptr;    // [H, D, npad]
   float* sq = nullptr;       // [H, nblk]
   float* sk = nullptr;
   float* sv = nullptr;
@@ -259,10 +270,15 @@ struct Ws {
 };
 
 struct WsShape {
-  int64_t n_tokens, npad, nblk, chunk_rows;
+  int64_t n_tokens = 0;  // N
+  int64_t rows = 0;      // largest row range of token-local work
+  int64_t vt_cols = 0;   // columns of vt
+  int64_t npad = 0;      // FP8: columns of v8t (padded scene layout)
+  int64_t nblk = 0;      // FP8: scale blocks per head
+  bool with_x = true;
 };
 
-Ws carve(const vggtx_config& c, const WsShape& sh, vggtx_prec prec, char* base, bool with_x = true) {
+Ws carve(const vggtx_config& c, const WsShape& sh, vggtx_prec prec, char* base) {
   Ws w;
   size_t off = 0;
   auto take = [&](size_t bytes) -> void* {
@@ -270,21 +286,25 @@ Ws carve(const vggtx_config& c, const WsShape& sh, vggtx_prec prec, char* base, 
     off += (size_t)round_up((int64_t)bytes, 256);
     return p;
   };
-  const int64_t N = sh.n_tokens, C = c.dim, F = c.mlp_hidden, R = sh.chunk_rows;
+  const int64_t N = sh.n_tokens, C = c.dim, F = c.mlp_hidden, R = sh.rows, H = c.heads;
   const size_t el = prec == VGGTX_F32 ? 4 : 2;
-  if (with_x) w.x = (float*)take(N * C * 4);
-  w.q = take(N * C * el);
-  w.k = take(N * C * el);
-  w.v = take(N * C * el);
-  if (prec != VGGTX_F32) w.vt = (bf16*)take(C * sh.npad * 2);
-  w.o = take(N * C * el);
+  if (sh.with_x) w.x = (float*)take(N * C * 4);
+  if (prec == VGGTX_FP8_E4M3) {
+    w.q = take(R * C * 2);
+    w.k = take(R * C * 2);
+  } else {
+    w.q = take(N * C * el);
+    w.k = take(N * C * el);
+  }
+  w.v = take((prec == VGGTX_F32 ? N : R) * C * el);
+  if (prec != VGGTX_F32) w.vt = (bf16*)take(C * sh.vt_cols * 2);
   w.h = take(R * C * el);
   w.hid = take(R * F * el);
   if (prec == VGGTX_FP8_E4M3) {
+    w.o = take(N * C * 2);
     w.q8 = (uint8_t*)take(N * C);
     w.k8 = (uint8_t*)take(N * C);
     w.v8t = (uint8_t*)take(C * sh.npad);
-    const int64_t H = c.heads;
     w.sq = (float*)take(H * sh.nblk * 4);
     w.sk = (float*)take(H * sh.nblk * 4);
     w.sv = (float*)take(H * sh.nblk * 4);
@@ -306,6 +326,7 @@ vggtx_status check_cfg(const vggtx_config* c) {
     return fail(VGGTX_E_UNSUPPORTED, "mlp_hidden %d: must be a positive multiple of 128", c->mlp_hidden);
   if (!(c->ln_eps > 0.f)) return fail(VGGTX_E_INVALID, "ln_eps must be positive");
   if (c->frame_chunk <= 0) return fail(VGGTX_E_INVALID, "frame_chunk must be positive");
+  if (c->tokens_inplace != 0 && c->tokens_inplace != 1) return fail(VGGTX_E_INVALID, "tokens_inplace must be 0 or 1");
   return VGGTX_OK;
 }
 
@@ -313,7 +334,6 @@ vggtx_status check_prec(vggtx_prec p) {
   if (p != VGGTX_F32 && p != VGGTX_BF16 && p != VGGTX_FP8_E4M3) return fail(VGGTX_E_INVALID, "unknown precision %d", (int)p);
   return VGGTX_OK;
 }
-
 vggtx_status check_block_w(const vggtx_block_w& w, const char* what, int layer) {
   const void* ptrs[12] = {w.ln1_g, w.ln1_b, w.w_qkv, w.b_qkv, w.w_o, w.b_o, w.ln2_g, w.ln2_b, w.w_fc1, w.b_fc1, w.w_fc2, w.b_fc2};
   for (int i = 0; i < 12; ++i) {
@@ -326,30 +346,40 @@ vggtx_status check_block_w(const vggtx_block_w& w, const char* what, int layer) 
 // Largest number of tokens whose indices the kernels address with 32-bit ints.
 constexpr int64_t kMaxTokens = (int64_t)1 << 30;
 
+
 // -------------------------------------------------------------- block forward
 struct BlockRun {
   vggtx_ctx* ctx;
   vggtx_prec prec;
   Ws ws;
+  WsShape sh;
   int64_t N;           // tokens in the x buffer
   hipStream_t stream;
 };
 
 inline bool lowp(vggtx_prec p) { return p != VGGTX_F32; }
 
-// out phase over rows [r0, r1): x += O W_o^T + b_o; x += MLP(LN2(x)); optional output copy
-vggtx_status out_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, int64_t r1, void* out, int64_t ldo,
-                       bool out_f32) {
+// Head-major [H, tokens, D] view: element (h, t, d) at p + (h * hs + t * D + d)
+// elements, t counted from the view's first token.
+struct HView {
+  void* p;
+  int64_t hs;
+};
+inline HView hv_at(HView v, int64_t t, size_t el) { return HView{(char*)v.p + t * kHeadDim * (int64_t)el, v.hs}; }
+
+// Output phase over rows [r0, r1): x += O W_o^T + b_o (O read head-major from
+// `o`, whose first token is row r0); x += MLP(LN2(x)); optional output copy.
+vggtx_status out_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, int64_t r1, HView o, void* out,
+                       int64_t ldo, bool out_f32) {
   const vggtx_config& c = br.ctx->cfg;
   const int C = c.dim, F = c.mlp_hidden;
   const bool lp = lowp(br.prec);
-  const size_t el = lp ? 2 : 4;
   auto gemm = lp ? launch_gemm_bf16 : launch_gemm_f32;
   const int M = (int)(r1 - r0);
   GemmParams g;
   memset(&g, 0, sizeof(g));
-  g.a = (const char*)br.ws.o + r0 * C * el;
-  g.lda = C;
+  g.a = o.p;
+  g.a_hs = o.hs;
   g.w = w.w_o;
   g.bias = w.b_o;
   g.M = M; g.N = C; g.K = C;
@@ -387,8 +417,9 @@ vggtx_status out_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, i
   return VGGTX_OK;
 }
 
-// LN1 + QKV projection of rows [r0, r1) into the head-major q/k/v buffers.
-vggtx_status qkv_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, int64_t r1) {
+// LN1 + QKV projection of rows [r0, r1) into the head-major views q, k, v
+// (each starting at row r0).
+vggtx_status qkv_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, int64_t r1, HView q, HView k, HView v) {
   const vggtx_config& c = br.ctx->cfg;
   const int C = c.dim;
   const bool lp = lowp(br.prec);
@@ -403,17 +434,20 @@ vggtx_status qkv_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, i
   g.w = w.w_qkv; g.bias = w.b_qkv;
   g.M = M; g.N = 3 * C; g.K = C;
   g.row0 = (int)r0;
-  g.q = br.ws.q; g.k = br.ws.k; g.v = br.ws.v;
-  g.qkv_hs = br.N * kHeadDim;
+  g.qkv[0] = q.p; g.qkv[1] = k.p; g.qkv[2] = v.p;
+  g.qkv_hs[0] = q.hs; g.qkv_hs[1] = k.hs; g.qkv_hs[2] = v.hs;
   g.C = C;
+  g.q_scale = 1.f;
   Span sp(br.ctx, VGGTX_K_GEMM, 2.0 * M * 3 * C * C, br.stream);
   VGGTX_HIP((lp ? launch_gemm_bf16 : launch_gemm_f32)(g, EPI_QKV, br.stream));
   return VGGTX_OK;
 }
 
-
 // Operands of one attention pass: q/k/v/o with their strides plus the
 // workspace pieces the BF16 (vt) and FP8 (codes, scales) kernels need.
+// `prepared` says that vt (BF16) or the codes and block scales (FP8) already
+// hold this pass's V / Q, K, V, so only the attention itself (and, for FP8,
+// the per-head scale table) is launched.
 struct AttnIO {
   const void* q; int64_t q_ts, q_hs;
   const void* k; int64_t k_ts, k_hs;
@@ -426,6 +460,7 @@ struct AttnIO {
   int64_t npad;     // columns of vt / v8t
   int64_t nblk;     // per-head stride of the FP8 scale arrays
   int64_t n_tokens; // rows of the q8 / k8 code arrays
+  bool prepared;
 };
 
 double table_flops(const SeqTable& t, int H) {
@@ -437,8 +472,9 @@ double table_flops(const SeqTable& t, int H) {
 }
 
 // Attention over the sequence set `s`: o = softmax(q k^T / sqrt(D)) v per
-// sequence and head.  `prec` picks the kernel; FP8 quantises q, k, v into
-// the workspace first (per-sequence 128-row blocks), BF16 transposes v.
+// sequence and head.  `prec` picks the kernel; unless io.prepared, FP8
+// quantises q, k, v into the workspace first (per-sequence 128-row blocks)
+// and BF16 transposes v.
 vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs& s, int H, vggtx_prec prec,
                            hipStream_t st) {
   AttnParams p;
@@ -458,7 +494,7 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
   }
   p.vt_hs = (int64_t)kHeadDim * io.npad; p.vt_ds = io.npad;
   if (prec == VGGTX_BF16) {
-    {
+    if (!io.prepared) {
       Span sp(ctx, VGGTX_K_OTHER, 0.0, st);
       for (auto& tn : make_tables(s, 64))
         VGGTX_HIP(launch_v_transpose_bf16((const bf16*)io.v, io.v_ts, io.v_hs, io.vt, p.vt_hs, p.vt_ds, tn.first,
@@ -479,14 +515,16 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
   const int64_t N = io.n_tokens;
   {
     Span sp(ctx, VGGTX_K_OTHER, 0.0, st);
-    for (auto& tn : make_tables(s, kQuantRows)) {
-      // Q carries log2(e)/sqrt(D), so that the logits come out in base 2
-      VGGTX_HIP(launch_quant_fp8((const bf16*)io.q, io.q_ts, io.q_hs, p.scale_log2, io.q8, N * kHeadDim, 0, false,
-                                 io.sq, io.nblk, tn.first, tn.second, H, st));
-      VGGTX_HIP(launch_quant_fp8((const bf16*)io.k, io.k_ts, io.k_hs, 1.f, io.k8, N * kHeadDim, 0, false, io.sk,
-                                 io.nblk, tn.first, tn.second, H, st));
-      VGGTX_HIP(launch_quant_fp8((const bf16*)io.v, io.v_ts, io.v_hs, 1.f, io.v8t, (int64_t)kHeadDim * io.npad,
-                                 io.npad, true, io.sv, io.nblk, tn.first, tn.second, H, st));
+    if (!io.prepared) {
+      for (auto& tn : make_tables(s, kQuantRows)) {
+        // Q carries log2(e)/sqrt(D), so that the logits come out in base 2
+        VGGTX_HIP(launch_quant_fp8((const bf16*)io.q, io.q_ts, io.q_hs, p.scale_log2, io.q8, N * kHeadDim, 0, false,
+                                   0, io.sq, io.nblk, tn.first, tn.second, H, st));
+        VGGTX_HIP(launch_quant_fp8((const bf16*)io.k, io.k_ts, io.k_hs, 1.f, io.k8, N * kHeadDim, 0, false, 0, io.sk,
+                                   io.nblk, tn.first, tn.second, H, st));
+        VGGTX_HIP(launch_quant_fp8((const bf16*)io.v, io.v_ts, io.v_hs, 1.f, io.v8t, (int64_t)kHeadDim * io.npad,
+                                   io.npad, true, 0, io.sv, io.nblk, tn.first, tn.second, H, st));
+      }
     }
     VGGTX_HIP(launch_scale_max(io.sk, io.sv, io.nblk, (int)s.scale_blocks(), io.vmax, io.kinfo, H, st));
   }
@@ -503,49 +541,146 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
   return VGGTX_OK;
 }
 
-// Attention of a block over the sequence set `s` from the head-major q/k/v
-// workspace buffers into o [N, C].
-vggtx_status attn_phase(const BlockRun& br, const Seqs& s, bool fp8, int64_t npad, int64_t nblk, int cls) {
-  const vggtx_config& c = br.ctx->cfg;
-  const int64_t N = br.N;
-  AttnIO io;
-  memset(&io, 0, sizeof(io));
-  io.q = br.ws.q; io.q_ts = kHeadDim; io.q_hs = N * kHeadDim;
-  io.k = br.ws.k; io.k_ts = kHeadDim; io.k_hs = N * kHeadDim;
-  io.v = br.ws.v; io.v_ts = kHeadDim; io.v_hs = N * kHeadDim;
-  io.o = br.ws.o; io.o_ts = c.dim; io.o_hs = kHeadDim;
-  io.vt = br.ws.vt;
-  io.q8 = br.ws.q8; io.k8 = br.ws.k8; io.v8t = br.ws.v8t;
-  io.sq = br.ws.sq; io.sk = br.ws.sk; io.sv = br.ws.sv; io.vmax = br.ws.vmax; io.kinfo = br.ws.kinfo;
-  io.npad = npad; io.nblk = nblk; io.n_tokens = N;
-  const vggtx_prec prec = br.prec == VGGTX_F32 ? VGGTX_F32 : (fp8 ? VGGTX_FP8_E4M3 : VGGTX_BF16);
-  return run_attention(br.ctx, cls, io, s, c.heads, prec, br.stream);
+// A row range of the global block's token-local work that lies inside one
+// sequence and starts a multiple of 128 rows after the sequence start (so
+// that FP8 scale blocks and 64-column V tiles never straddle two pieces).
+struct Piece {
+  int64_t r0, r1;  // rows
+  int64_t col;     // padded column of row r0 in the transposed V layout of the sequence set
+  int64_t blk;     // FP8 scale block of row r0
+};
+
+std::vector<Piece> make_pieces(const Seqs& s, int64_t max_rows) {
+  std::vector<Piece> out;
+  const int64_t step = std::max<int64_t>(kQuantRows, max_rows / kQuantRows * kQuantRows);
+  int64_t col = 0, blk = 0;
+  for (int i = 0; i < s.n; ++i) {
+    int64_t a, b;
+    if (s.uniform) {
+      a = s.first + (int64_t)i * s.len;
+      b = a + s.len;
+      col = (int64_t)(s.first_index + i) * round_up(s.len, kKeyPad);
+      blk = (int64_t)(s.first_index + i) * cdiv(s.len, kQuantRows);
+    } else {
+      a = s.start[i];
+      b = s.end[i];
+    }
+    for (int64_t p0 = a; p0 < b; p0 += step)
+      out.push_back(Piece{p0, std::min(b, p0 + step), col + (p0 - a), blk + (p0 - a) / kQuantRows});
+    if (!s.uniform) {
+      col += round_up(b - a, kKeyPad);
+      blk += cdiv(b - a, kQuantRows);
+    }
+  }
+  return out;
+}
+
+// Launch table of one piece: a single sequence of r1 - r0 rows counted from
+// 0 (the piece's staging rows), placed at column `col` / block `blk`.
+std::pair<SeqTable, int> piece_table(const Piece& pc, int rows) {
+  SeqTable t;
+  memset(&t, 0, sizeof(t));
+  t.uniform = 0;
+  t.n_seq = 1;
+  t.start[0] = 0;
+  t.end[0] = (int)(pc.r1 - pc.r0);
+  t.vt_base[0] = (int)pc.col;
+  t.blk_base[0] = (int)pc.blk;
+  t.tile_end[0] = (int)cdiv(pc.r1 - pc.r0, rows);
+  return {t, t.tile_end[0]};
 }
 
 // One block whose attention spans the sequence set `seqs` (rows [0, N) of x):
-// QKV for every chunk, one attention pass, then the output phase per chunk.
-vggtx_status block_global(const BlockRun& br, const vggtx_block_w& w, const Seqs& seqs, int64_t chunk_rows, bool fp8,
-                          int64_t npad, int64_t nblk, void* out, int64_t ldo, bool out_f32) {
-  for (int64_t r0 = 0; r0 < br.N; r0 += chunk_rows) VGGTX_TRY(qkv_phase(br, w, r0, std::min(br.N, r0 + chunk_rows)));
-  VGGTX_TRY(attn_phase(br, seqs, fp8, npad, nblk, VGGTX_K_ATTN_GLOBAL));
-  for (int64_t r0 = 0; r0 < br.N; r0 += chunk_rows)
-    VGGTX_TRY(out_phase(br, w, r0, std::min(br.N, r0 + chunk_rows), out, ldo, out_f32));
+// LN1 + QKV piece by piece (BF16: V transposed into its attention layout per
+// piece; FP8: Q, K, V quantised per piece), one attention pass over every
+// sequence, then the output phase piece by piece.
+vggtx_status block_global(const BlockRun& br, const vggtx_block_w& w, const Seqs& seqs, void* out, int64_t ldo,
+                          bool out_f32) {
+  const vggtx_config& c = br.ctx->cfg;
+  const int H = c.heads;
+  const int64_t N = br.N, R = br.sh.rows;
+  const size_t el = lowp(br.prec) ? 2 : 4;
+  const bool fp8 = br.prec == VGGTX_FP8_E4M3;
+  const std::vector<Piece> pieces = make_pieces(seqs, R);
+  const HView q{br.ws.q, (fp8 ? R : N) * kHeadDim}, k{br.ws.k, (fp8 ? R : N) * kHeadDim};
+  const HView v{br.ws.v, (br.prec == VGGTX_F32 ? N : R) * kHeadDim};
+  hipStream_t st = br.stream;
+  for (const Piece& pc : pieces) {
+    const int64_t t0 = fp8 ? 0 : pc.r0;  // first row of the piece in the q / k views
+    VGGTX_TRY(qkv_phase(br, w, pc.r0, pc.r1, hv_at(q, t0, el), hv_at(k, t0, el),
+                        hv_at(v, br.prec == VGGTX_F32 ? pc.r0 : 0, el)));
+    if (br.prec == VGGTX_BF16) {
+      Span sp(br.ctx, VGGTX_K_OTHER, 0.0, st);
+      const auto tn = piece_table(pc, 64);
+      VGGTX_HIP(launch_v_transpose_bf16((const bf16*)v.p, kHeadDim, v.hs, br.ws.vt, kHeadDim * br.sh.vt_cols,
+                                        br.sh.vt_cols, tn.first, tn.second, H, st));
+    } else if (fp8) {
+      Span sp(br.ctx, VGGTX_K_OTHER, 0.0, st);
+      const auto tn = piece_table(pc, kQuantRows);
+      const float c2 = kLog2e / sqrtf((float)kHeadDim);
+      // Q carries log2(e)/sqrt(D), so that the logits come out in base 2
+      VGGTX_HIP(launch_quant_fp8((const bf16*)q.p, kHeadDim, q.hs, c2, br.ws.q8, N * kHeadDim, 0, false, pc.r0,
+                                 br.ws.sq, br.sh.nblk, tn.first, tn.second, H, st));
+      VGGTX_HIP(launch_quant_fp8((const bf16*)k.p, kHeadDim, k.hs, 1.f, br.ws.k8, N * kHeadDim, 0, false, pc.r0,
+                                 br.ws.sk, br.sh.nblk, tn.first, tn.second, H, st));
+      VGGTX_HIP(launch_quant_fp8((const bf16*)v.p, kHeadDim, v.hs, 1.f, br.ws.v8t, kHeadDim * br.sh.npad, br.sh.npad,
+                                 true, 0, br.ws.sv, br.sh.nblk, tn.first, tn.second, H, st));
+    }
+  }
+  AttnIO io;
+  memset(&io, 0, sizeof(io));
+  io.q = q.p; io.q_ts = kHeadDim; io.q_hs = q.hs;
+  io.k = k.p; io.k_ts = kHeadDim; io.k_hs = k.hs;
+  io.v = v.p; io.v_ts = kHeadDim; io.v_hs = v.hs;
+  // BF16 / F32: O goes over Q (each work item reads its query rows before it
+  // writes their outputs, and no other item reads them); FP8: its own buffer
+  const HView o = fp8 ? HView{br.ws.o, N * kHeadDim} : q;
+  io.o = o.p; io.o_ts = kHeadDim; io.o_hs = o.hs;
+  io.vt = br.ws.vt;
+  io.q8 = br.ws.q8; io.k8 = br.ws.k8; io.v8t = br.ws.v8t;
+  io.sq = br.ws.sq; io.sk = br.ws.sk; io.sv = br.ws.sv; io.vmax = br.ws.vmax; io.kinfo = br.ws.kinfo;
+  io.npad = fp8 ? br.sh.npad : br.sh.vt_cols;
+  io.nblk = br.sh.nblk;
+  io.n_tokens = N;
+  io.prepared = true;
+  VGGTX_TRY(run_attention(br.ctx, VGGTX_K_ATTN_GLOBAL, io, seqs, H, br.prec, st));
+  for (const Piece& pc : pieces)
+    VGGTX_TRY(out_phase(br, w, pc.r0, pc.r1, hv_at(o, pc.r0, el), out, ldo, out_f32));
   return VGGTX_OK;
 }
 
 // Frame block: chunks of whole frames; every chunk runs QKV, frame attention
 // and the output phase before the next chunk starts (Sec. 3.2, chunked
-// frame-wise processing).
-vggtx_status block_frames(const BlockRun& br, const vggtx_block_w& w, int S, int P, int frame_chunk, int64_t npad,
-                          int64_t nblk, void* out, int64_t ldo, bool out_f32) {
+// frame-wise processing).  Frame attention runs on bfloat16 operands in the
+// FP8 mode too; its Q, K, V, O and transposed V are chunk-relative.
+vggtx_status block_frames(const BlockRun& br, const vggtx_block_w& w, int S, int P, int frame_chunk, void* out,
+                          int64_t ldo, bool out_f32) {
+  const vggtx_config& c = br.ctx->cfg;
+  const int64_t N = br.N, R = br.sh.rows;
+  const size_t el = lowp(br.prec) ? 2 : 4;
+  const bool fp8 = br.prec == VGGTX_FP8_E4M3;
+  const HView q{br.ws.q, (fp8 ? R : N) * kHeadDim}, k{br.ws.k, (fp8 ? R : N) * kHeadDim};
+  const HView v{br.ws.v, (br.prec == VGGTX_F32 ? N : R) * kHeadDim};
   for (int f0 = 0; f0 < S; f0 += frame_chunk) {
     const int f1 = std::min(S, f0 + frame_chunk);
     const int64_t r0 = (int64_t)f0 * P, r1 = (int64_t)f1 * P;
-    VGGTX_TRY(qkv_phase(br, w, r0, r1));
+    const HView qc = hv_at(q, fp8 ? 0 : r0, el), kc = hv_at(k, fp8 ? 0 : r0, el);
+    const HView vc = hv_at(v, br.prec == VGGTX_F32 ? r0 : 0, el);
+    VGGTX_TRY(qkv_phase(br, w, r0, r1, qc, kc, vc));
     Seqs fr;
-    fr.uniform = true; fr.first = (int)r0; fr.len = P; fr.n = f1 - f0; fr.first_index = f0;
-    VGGTX_TRY(attn_phase(br, fr, false, npad, nblk, VGGTX_K_ATTN_FRAME));
-    VGGTX_TRY(out_phase(br, w, r0, r1, out, ldo, out_f32));
+    fr.uniform = true; fr.first = 0; fr.len = P; fr.n = f1 - f0; fr.first_index = 0;
+    AttnIO io;
+    memset(&io, 0, sizeof(io));
+    io.q = qc.p; io.q_ts = kHeadDim; io.q_hs = qc.hs;
+    io.k = kc.p; io.k_ts = kHeadDim; io.k_hs = kc.hs;
+    io.v = vc.p; io.v_ts = kHeadDim; io.v_hs = vc.hs;
+    io.o = qc.p; io.o_ts = kHeadDim; io.o_hs = qc.hs;  // O over Q
+    io.vt = br.ws.vt;
+    io.npad = br.sh.vt_cols;
+    io.n_tokens = r1 - r0;
+    VGGTX_TRY(run_attention(br.ctx, VGGTX_K_ATTN_FRAME, io, fr, c.heads,
+                            br.prec == VGGTX_F32 ? VGGTX_F32 : VGGTX_BF16, br.stream));
+    VGGTX_TRY(out_phase(br, w, r0, r1, qc, out, ldo, out_f32));
   }
   return VGGTX_OK;
 }
@@ -573,13 +708,19 @@ Seqs seqs_from_offsets(const int32_t* off, int n, int scale) {
   return s;
 }
 
-WsShape agg_shape(const vggtx_config& c, int64_t total_frames, int P) {
+// Workspace shape of a forward over `total_frames` frames of P tokens (any
+// partition into scenes): padded columns and scale blocks of the frame-wise
+// partition bound those of every coarser one.
+WsShape agg_shape(const vggtx_config& c, int64_t total_frames, int P, vggtx_prec prec, bool with_x) {
   WsShape sh;
   sh.n_tokens = total_frames * P;
-  // padded columns of frame-wise sets bound those of any scene partition
-  sh.npad = total_frames * round_up(P, kKeyPad);
+  sh.rows = std::max<int64_t>(kQuantRows, std::min<int64_t>(total_frames, c.frame_chunk) * P);
+  const int64_t ppad = round_up(P, kKeyPad);
+  // FP8: vt serves the frame chunks only (global attention reads v8t)
+  sh.vt_cols = (prec == VGGTX_FP8_E4M3 ? std::min<int64_t>(total_frames, c.frame_chunk) : total_frames) * ppad;
+  sh.npad = total_frames * ppad;
   sh.nblk = total_frames * cdiv(P, kQuantRows);
-  sh.chunk_rows = std::min<int64_t>(total_frames, c.frame_chunk) * P;
+  sh.with_x = with_x;
   return sh;
 }
 
@@ -610,7 +751,7 @@ vggtx_status aggregate_impl(vggtx_handle h, const float* tokens, const int32_t* 
     VGGTX_TRY(check_block_w(w[l].frame, "frame", l));
     VGGTX_TRY(check_block_w(w[l].global, "global", l));
   }
-  const WsShape sh = agg_shape(c, S, P);
+  const WsShape sh = agg_shape(c, S, P, prec, !c.tokens_inplace);
   const Ws need = carve(c, sh, prec, nullptr);
   if (!ws || ws_bytes < need.total)
     return fail(VGGTX_E_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need.total);
@@ -622,10 +763,14 @@ vggtx_status aggregate_impl(vggtx_handle h, const float* tokens, const int32_t* 
   br.ctx = h;
   br.prec = prec;
   br.ws = carve(c, sh, prec, (char*)ws);
+  br.sh = sh;
   br.N = N;
   br.stream = (hipStream_t)stream;
   const int C = c.dim;
-  VGGTX_HIP(launch_copy_f32(tokens, br.ws.x, N * C, br.stream));
+  if (c.tokens_inplace)
+    br.ws.x = const_cast<float*>(tokens);  // the caller handed the buffer over (vggtx_config.tokens_inplace)
+  else
+    VGGTX_HIP(launch_copy_f32(tokens, br.ws.x, N * C, br.stream));
   const Seqs scenes = seqs_from_offsets(frame_offsets, n_scenes, P);
   const bool out_f32 = out_dtype == VGGTX_OUT_F32;
   const size_t oel = out_f32 ? 4 : 2;
@@ -633,9 +778,8 @@ vggtx_status aggregate_impl(vggtx_handle h, const float* tokens, const int32_t* 
   for (int l = 0; l <= last; ++l) {
     const bool keep = out_layers[slot] == l;
     char* ob = keep ? (char*)out + (size_t)slot * N * 2 * C * oel : nullptr;
-    VGGTX_TRY(block_frames(br, w[l].frame, (int)S, P, c.frame_chunk, sh.npad, sh.nblk, ob, 2 * C, out_f32));
-    VGGTX_TRY(block_global(br, w[l].global, scenes, sh.chunk_rows, prec == VGGTX_FP8_E4M3, sh.npad, sh.nblk,
-                           ob ? ob + (size_t)C * oel : nullptr, 2 * C, out_f32));
+    VGGTX_TRY(block_frames(br, w[l].frame, (int)S, P, c.frame_chunk, ob, 2 * C, out_f32));
+    VGGTX_TRY(block_global(br, w[l].global, scenes, ob ? ob + (size_t)C * oel : nullptr, 2 * C, out_f32));
     if (keep) ++slot;
   }
   return VGGTX_OK;
@@ -728,10 +872,8 @@ EmbedPlan embed_plan(const vggtx_config& c, int64_t total_frames, int height, in
   e.n_patch = (height / kEmbedPatch) * (width / kEmbedPatch);
   e.Pd = kEmbedSpecial + e.n_patch;
   e.fc = std::max<int64_t>(1, std::min<int64_t>({total_frames, (int64_t)c.frame_chunk, (int64_t)kEmbedMaxChunk}));
-  e.sh.n_tokens = e.fc * e.Pd;
-  e.sh.npad = e.fc * round_up(e.Pd, kKeyPad);
-  e.sh.nblk = e.fc * cdiv(e.Pd, kQuantRows);
-  e.sh.chunk_rows = e.fc * e.Pd;
+  e.sh = agg_shape(c, e.fc, e.Pd, prec, true);
+  e.sh.rows = std::max<int64_t>(kQuantRows, e.fc * e.Pd);
   e.ws = carve(c, e.sh, prec, base);
   const size_t el = prec == VGGTX_F32 ? 4 : 2;
   size_t off = (size_t)round_up((int64_t)e.ws.total, 256);
@@ -803,6 +945,7 @@ vggtx_status embed_impl(vggtx_handle h, const float* images, int height, int wid
     br.ctx = h;
     br.prec = pr;
     br.ws = e.ws;
+    br.sh = e.sh;
     br.N = (int64_t)nf * e.Pd;
     br.stream = st;
     {
@@ -822,7 +965,7 @@ vggtx_status embed_impl(vggtx_handle h, const float* images, int height, int wid
       VGGTX_HIP((lp ? launch_gemm_bf16 : launch_gemm_f32)(g, EPI_EMBED, st));
     }
     for (int l = 0; l < w->depth; ++l)
-      VGGTX_TRY(block_frames(br, w->blocks[l], nf, e.Pd, nf, e.sh.npad, e.sh.nblk, nullptr, 0, false));
+      VGGTX_TRY(block_frames(br, w->blocks[l], nf, e.Pd, nf, nullptr, 0, false));
     FirstMask fm;
     memset(&fm, 0, sizeof(fm));
     for (int f = 0; f < nf; ++f)
@@ -1019,7 +1162,7 @@ vggtx_status vggtx_create(vggtx_handle* h, int device, const vggtx_config* cfg) 
 
 vggtx_status vggtx_destroy(vggtx_handle h) {
   if (!h) return VGGTX_OK;
-  for (auto& e : h->timer.ev) (void)hipEventDestroy(e);
+  for (int i = 0; i < 2 * h->timer.created; ++i) (void)hipEventDestroy(h->timer.ev[i]);
   delete h;
   return VGGTX_OK;
 }
@@ -1028,7 +1171,7 @@ vggtx_status vggtx_workspace_size(vggtx_handle h, int total_frames, int P, vggtx
   if (!h || !bytes) return fail(VGGTX_E_INVALID, "handle / bytes is null");
   VGGTX_TRY(check_prec(prec));
   if (total_frames < 0 || P <= 0) return fail(VGGTX_E_INVALID, "frames %d, P %d", total_frames, P);
-  *bytes = carve(h->cfg, agg_shape(h->cfg, total_frames, P), prec, nullptr).total;
+  *bytes = carve(h->cfg, agg_shape(h->cfg, total_frames, P, prec, !h->cfg.tokens_inplace), prec, nullptr).total;
   return VGGTX_OK;
 }
 
@@ -1063,8 +1206,8 @@ vggtx_status vggtx_block(vggtx_handle h, const float* x_in, float* x_out, const 
   if ((uintptr_t)x_in % 16 || (uintptr_t)x_out % 16) return fail(VGGTX_E_INVALID, "x must be 16-byte aligned");
   int lmax = 0;
   for (int i = 0; i < n_seq; ++i) lmax = std::max(lmax, seq_offsets[i + 1] - seq_offsets[i]);
-  const WsShape sh = agg_shape(c, n_seq, lmax);
-  const Ws need = carve(c, sh, prec, nullptr, false);
+  const WsShape sh = agg_shape(c, n_seq, lmax, prec, false);
+  const Ws need = carve(c, sh, prec, nullptr);
   if (!ws || ws_bytes < need.total)
     return fail(VGGTX_E_WORKSPACE, "workspace %zu bytes, need %zu", ws ? ws_bytes : (size_t)0, need.total);
   if ((uintptr_t)ws % 256) return fail(VGGTX_E_INVALID, "workspace must be 256-byte aligned");
@@ -1073,14 +1216,14 @@ vggtx_status vggtx_block(vggtx_handle h, const float* x_in, float* x_out, const 
   BlockRun br;
   br.ctx = h;
   br.prec = prec;
-  br.ws = carve(c, sh, prec, (char*)ws, false);
+  br.ws = carve(c, sh, prec, (char*)ws);
   br.ws.x = x_out;
+  br.sh = sh;
   br.N = N;
   br.stream = (hipStream_t)stream;
-  VGGTX_HIP(launch_copy_f32(x_in, x_out, N * c.dim, br.stream));
+  if (x_in != x_out) VGGTX_HIP(launch_copy_f32(x_in, x_out, N * c.dim, br.stream));
   const Seqs s = seqs_from_offsets(seq_offsets, n_seq, 1);
-  const int64_t chunk_rows = std::max<int64_t>(1, std::min<int64_t>(N, (int64_t)c.frame_chunk * std::max(1, lmax)));
-  return block_global(br, *w, s, chunk_rows, prec == VGGTX_FP8_E4M3, sh.npad, sh.nblk, nullptr, 0, false);
+  return block_global(br, *w, s, nullptr, 0, false);
 }
 
 vggtx_status vggtx_embed_workspace_size(vggtx_handle h, int total_frames, int height, int width, vggtx_prec prec,
@@ -1267,7 +1410,7 @@ vggtx_status vggtx_quantize_fp8(vggtx_handle h, const void* x, vggtx_layout in_l
   const int64_t nblk = s.scale_blocks();
   for (auto& tn : make_tables(s, kQuantRows))
     VGGTX_HIP(launch_quant_fp8((const bf16*)x, in_layout.token_stride, in_layout.head_stride, 1.f, codes,
-                               N * kHeadDim, 0, false, scales, nblk, tn.first, tn.second, H, (hipStream_t)stream));
+                               N * kHeadDim, 0, false, 0, scales, nblk, tn.first, tn.second, H, (hipStream_t)stream));
   return VGGTX_OK;
 }
 
@@ -1403,12 +1546,12 @@ vggtx_status vggtx_timing_enable(vggtx_handle h, int enable) {
   if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
   KernelTimer& t = h->timer;
   if (enable && t.ev.empty()) {
-    t.ev.resize(2 * KernelTimer::kEventBlock);
-    for (auto& e : t.ev) VGGTX_HIP(hipEventCreate(&e));
+    t.ev.assign(2 * (size_t)KernelTimer::kMaxRec, nullptr);
+    t.cls.assign(KernelTimer::kMaxRec, 0);
+    t.flops.assign(KernelTimer::kMaxRec, 0.0);
   }
   t.enabled = enable != 0;
-  t.cls.clear();
-  t.flops.clear();
+  t.n.store(0, std::memory_order_release);
   t.dropped = 0;
   return VGGTX_OK;
 }
@@ -1417,9 +1560,10 @@ vggtx_status vggtx_timing_poll(vggtx_handle h, int64_t* finished, int64_t* recor
   if (!h || !finished || !recorded) return fail(VGGTX_E_INVALID, "handle / output is null");
   DeviceGuard dg(h->device);
   if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
-  KernelTimer& t = h->timer;
+  const KernelTimer& t = h->timer;
+  const int n = t.n.load(std::memory_order_acquire);
   int64_t done = 0, ga = 0;
-  for (size_t i = 0; i < t.cls.size(); ++i) {
+  for (int i = 0; i < n; ++i) {
     const hipError_t e = hipEventQuery(t.ev[2 * i + 1]);
     if (e == hipErrorNotReady) break;
     if (e != hipSuccess) return fail(VGGTX_E_HIP, "hipEventQuery: %s", hipGetErrorString(e));
@@ -1427,7 +1571,7 @@ vggtx_status vggtx_timing_poll(vggtx_handle h, int64_t* finished, int64_t* recor
     if (t.cls[i] == VGGTX_K_ATTN_GLOBAL) ++ga;
   }
   *finished = done;
-  *recorded = (int64_t)t.cls.size();
+  *recorded = n;
   if (finished_attn_global) *finished_attn_global = ga;
   return VGGTX_OK;
 }
@@ -1438,7 +1582,8 @@ vggtx_status vggtx_timing_read(vggtx_handle h, vggtx_timing out[VGGTX_K_COUNT], 
   if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
   KernelTimer& t = h->timer;
   for (int k = 0; k < VGGTX_K_COUNT; ++k) out[k] = vggtx_timing{0.0, 0, 0.0};
-  for (size_t i = 0; i < t.cls.size(); ++i) {
+  const int n = t.n.load(std::memory_order_acquire);
+  for (int i = 0; i < n; ++i) {
     VGGTX_HIP(hipEventSynchronize(t.ev[2 * i + 1]));
     float ms = 0.f;
     VGGTX_HIP(hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]));
@@ -1447,8 +1592,7 @@ vggtx_status vggtx_timing_read(vggtx_handle h, vggtx_timing out[VGGTX_K_COUNT], 
     out[t.cls[i]].flops += t.flops[i];
   }
   if (dropped) *dropped = t.dropped;
-  t.cls.clear();
-  t.flops.clear();
+  t.n.store(0, std::memory_order_release);
   t.dropped = 0;
   return VGGTX_OK;
 }

@@ -45,7 +45,8 @@ class VggtxError(RuntimeError):
 
 class Config(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("heads", ctypes.c_int), ("head_dim", ctypes.c_int),
-                ("mlp_hidden", ctypes.c_int), ("ln_eps", ctypes.c_float), ("frame_chunk", ctypes.c_int)]
+                ("mlp_hidden", ctypes.c_int), ("ln_eps", ctypes.c_float), ("frame_chunk", ctypes.c_int),
+                ("tokens_inplace", ctypes.c_int)]
 
 
 class BlockW(ctypes.Structure):
@@ -162,8 +163,9 @@ def _i32_array(vals: Sequence[int]):
 
 
 def create(device: int, dim: int, heads: int, head_dim: int = 64, mlp_hidden: Optional[int] = None,
-           ln_eps: float = 1e-6, frame_chunk: int = 128) -> ctypes.c_void_p:
-    cfg = Config(dim, heads, head_dim, mlp_hidden if mlp_hidden is not None else 4 * dim, ln_eps, frame_chunk)
+           ln_eps: float = 1e-6, frame_chunk: int = 128, tokens_inplace: bool = False) -> ctypes.c_void_p:
+    cfg = Config(dim, heads, head_dim, mlp_hidden if mlp_hidden is not None else 4 * dim, ln_eps, frame_chunk,
+                 1 if tokens_inplace else 0)
     h = ctypes.c_void_p()
     _check(load().vggtx_create(ctypes.byref(h), int(device), ctypes.byref(cfg)))
     return h
@@ -434,8 +436,9 @@ class Handle:
     """Owns a vggtx handle for one device and model shape."""
 
     def __init__(self, device: int = 0, dim: int = 1024, heads: int = 16, head_dim: int = 64,
-                 mlp_hidden: Optional[int] = None, ln_eps: float = 1e-6, frame_chunk: int = 128):
-        self.h = create(device, dim, heads, head_dim, mlp_hidden, ln_eps, frame_chunk)
+                 mlp_hidden: Optional[int] = None, ln_eps: float = 1e-6, frame_chunk: int = 128,
+                 tokens_inplace: bool = False):
+        self.h = create(device, dim, heads, head_dim, mlp_hidden, ln_eps, frame_chunk, tokens_inplace)
 
     def close(self):
         if self.h is not None:

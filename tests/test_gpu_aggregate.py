@@ -91,6 +91,42 @@ def test_chunking_is_bitwise_invariant():
         assert torch.equal(o, outs[0])
 
 
+@pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3])
+def test_chunking_is_bitwise_invariant_varlen(prec):
+    """Three scenes of 2, 3 and 2 frames of 86 tokens: frame chunks of 1, 3,
+    7 and 128 frames also change the scene-aligned pieces of the global
+    block's token-local work (128, 256 and 512 rows), in every precision."""
+    m = synth.ModelConfig(dim=128, heads=2, head_dim=64, mlp_hidden=256, depth=2)
+    S, P = 7, 86
+    tokens, layers = synth.gen_problem(m, S, P, seed=5, bf16=prec != vg.F32)
+    ld = weights_to_dev(layers, _dt(prec))
+    outs = [_run(_handle(m, chunk), tokens, ld, [0, 1], prec, [0, 2, 5, 7]) for chunk in (1, 3, 7, 128)]
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+@pytest.mark.parametrize("prec", [vg.BF16, vg.FP8_E4M3])
+def test_tokens_inplace_equals_copy(prec):
+    """With tokens_inplace the forward runs in the caller's tokens buffer:
+    the same outputs bit for bit, a workspace smaller by S*P*C*4 bytes, and
+    the buffer left holding the last layer's global-block output."""
+    m = synth.ModelConfig(dim=128, heads=2, head_dim=64, mlp_hidden=256, depth=2)
+    S, P = 3, 86
+    tokens, layers = synth.gen_problem(m, S, P, seed=6, bf16=True)
+    ld = weights_to_dev(layers, torch.bfloat16)
+    h0 = _handle(m)
+    ref = vg.aggregate(h0.h, to_dev(tokens, torch.float32), ld, [0, 1], prec, out_dtype=vg.OUT_F32)
+    h1 = vg.Handle(0, dim=m.dim, heads=m.heads, head_dim=m.head_dim, mlp_hidden=m.mlp_hidden, ln_eps=m.ln_eps,
+                   tokens_inplace=True)
+    assert vg.workspace_size(h0.h, S, P, prec) - vg.workspace_size(h1.h, S, P, prec) >= S * P * m.dim * 4
+    td = to_dev(tokens, torch.float32)
+    got = vg.aggregate(h1.h, td, ld, [0, 1], prec, out_dtype=vg.OUT_F32)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    assert torch.equal(td, ref[1, ..., m.dim:])
+    h0.close(); h1.close()
+
+
 def test_out_layer_subset_is_bitwise_slice():
     m = synth.ModelConfig(dim=128, heads=2, head_dim=64, mlp_hidden=256, depth=3)
     tokens, layers = synth.gen_problem(m, 3, 50, seed=2, bf16=True)
