@@ -55,7 +55,7 @@ typedef enum {
   VGGTX_E_NODEVICE = 5     /* no usable GPU / bad device ordinal */
 } vggtx_status;
 
-typedef enum { VGGTX_F32 = 0, VGGTX_BF16 = 1, VGGTX_FP8_E4M3 = 2 } vggtx_prec;
+typedef enum { VGGTX_F32 = 0, VGGTX_BF16 = 1, VGGTX_FP8_E4M3 = 2, VGGTX_FP8_PV = 3 } vggtx_prec;
 
 /* storage type of an output buffer */
 typedef enum { VGGTX_OUT_F32 = 0, VGGTX_OUT_BF16 = 1 } vggtx_dtype;
@@ -211,8 +211,8 @@ vggtx_status vggtx_quantize_fp8(vggtx_handle h, const void* x, vggtx_layout in_l
                                 uint8_t* codes, float* scales, void* stream);
 
 /* Attention autotuner.  Times every compiled tile variant of the attention
- * kernel for `prec` (VGGTX_BF16: variant 0 or 1 = 1 or 2 query blocks of
- * 32 rows per wave, 4 waves; VGGTX_FP8_E4M3: variants 0..3 = (query blocks
+ * kernel for `prec` (VGGTX_BF16: variants 0..2 = (query blocks of 32 rows per
+ * wave, waves per workgroup) (1,4), (2,4), (1,8); VGGTX_FP8_E4M3: variants 0..3 = (query blocks
  * per wave, waves per workgroup) (1,4), (2,4), (1,8), (2,8)) on synthetic
  * Q, K, V written into the
  * caller's workspace (one sequence of `n_tokens` tokens, 16 heads of 64; a

@@ -71,18 +71,69 @@ __device__ __forceinline__ float lane_swap_max(float v) {
   return __builtin_fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
 }
 
+// |x| >= the float whose bits are `bound`, NaN included, decided on the bits.
+// This file is built without NaN semantics, under which the compiler may turn
+// an integer test on a float's bits back into a float compare that a NaN
+// fails (it did: a test for "inf or NaN" became |x| == inf); the empty asm
+// makes the bits opaque to it.
+__device__ __forceinline__ bool abs_bits_at_least(float x, uint32_t bound) {
+  uint32_t u = __float_as_uint(x);
+  asm("" : "+v"(u));
+  return (u & 0x7fffffffu) >= bound;
+}
+
+// E4M3 conversion without a clamp: the hardware rounds to nearest even, so
+// values up to 464 give 448 and larger ones give the NaN code, which the
+// kernel below uses as its overflow signal.  Four floats -> four E4M3 codes
+// in one dword (bytes in argument order).  The first conversion fills the
+// low half (its high half is scratch), the second writes the high half in
+// place.
+__device__ __forceinline__ int pack_e4m3x4(float e0, float e1, float e2, float e3) {
+  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(e0, e1, __float_as_int(e0), false);
+  return __builtin_amdgcn_cvt_pk_fp8_f32(e2, e3, lo, true);
+}
+
 // ============================================================== BF16 kernel
 //
-// LDS tiles (BN = 64 keys, D = 64), 16-byte granules XOR-swizzled with the row
-// index to keep ds_read_b128 conflict free:
-//   Ks[key][d]      granule (d/8) ^ lds_swz8(key)
-//   Vs[d][key']     transposed V; inside every 16-key group the keys are
-//                   stored in the order in which a lane's MFMA k-slots need
-//                   them (slot j of lane group g <-> key 8*(j/4) + 4*g + j%4),
-//                   granule ^ lds_swz8(d).
-template <int QB, bool OUT_F32, int OCC>
-__global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
-  constexpr int BN = 64, D = kHeadDim, BM = 128 * QB;
+// LDS tiles (BN = 64 keys, D = 64, 128-byte rows), double-buffered.  Tiles
+// move from global memory straight into LDS (global_load_lds_dwordx4: lane l
+// of one instruction fills bytes 16l..16l+15 of a 1 KB LDS block, i.e. 8 tile
+// rows), so no registers stage them; the next tile's loads are issued once
+// every LDS read of the current tile's fragments is, and waited for at the
+// end of the tile, before the barrier.  The 16-byte granules of a row are
+// XOR-swizzled with the row index (lds_swz8), which keeps the ds_read_b128 of
+// the MFMA fragments conflict free.
+//   Ks[r][.]  K tile, row r holding key pi(r): rows 4..7 and 8..11 of every
+//             16 are swapped, so that the score MFMA leaves 8 consecutive keys
+//             in accumulator registers 0..7 (and 8..15) of each lane group
+//             (key of register i in lane group g: 16 (i / 8) + 8 g + i % 8);
+//             the probabilities then pack into the B operand of the P V
+//             product in key order.
+//   Vs[d][.]  V^T tile in key order.
+//
+// Softmax with a lazy shift.  Full key tiles after the first take the
+// probabilities against the current shift m (the largest logit seen when m
+// last moved), p = 2^(c2 s - c2 m), with no maximum search: softmax is
+// shift-invariant, so m only has to keep p finite.  While the tile's row sum
+// stays below 2^32 every p of the row is below it, and O and l (float32)
+// stay far from overflow.  A row sum at or above 2^32 (an infinity or a NaN
+// included; tested on the bits) sends the query block to the exact step: its
+// scores are recomputed from the K tile still in LDS, m moves to the row
+// maximum, O and l are rescaled by 2^(c2 m_old - c2 m_new), and the
+// probabilities are taken again.  The first and the partial last tile always
+// take the exact step.  The row sum runs on the matrix core: a 16x16x32 MFMA
+// with a lane-selector A operand over the bfloat16 probability registers of
+// the P V product (read as its B operand, they are 16 columns whose four
+// k-groups hold queries n, n+16, n, n+16; selector rows 4j..4j+3 take the
+// k-groups of parity j&1, so output lane l receives the sum for its own query
+// l%32), so l is summed from the same rounded probabilities as O.
+//
+// Issue order: the score MFMAs of query block qb+1 and the P V MFMAs of block
+// qb-1 are issued between the exponentials of block qb.
+template <int QB, int NW, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC) void attn_bf16_kernel(AttnParams p) {
+  constexpr int BN = 64, D = kHeadDim, BM = 32 * QB * NW;
+  constexpr float kLazyBound = 0x1p32f;
   __shared__ __attribute__((aligned(16))) bf16 Ks[2][BN * D];
   __shared__ __attribute__((aligned(16))) bf16 Vs[2][D * BN];
 
@@ -96,6 +147,8 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
   const bf16* Vt = (const bf16*)p.vt + head * p.vt_hs + it.vb;
 
   const bf16x8 zero8 = {};
+  const bf16 sv = (((lane >> 2) ^ (lane >> 4)) & 1) ? (bf16)0.0f : (bf16)1.0f;  // row-sum selector
+  const bf16x8 sel8 = {sv, sv, sv, sv, sv, sv, sv, sv};
   bf16x8 qf[QB][4];
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
@@ -105,37 +158,21 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
       qf[qb][c] = row < it.s1 ? *(const bf16x8*)(Q + row * p.q_ts + 16 * c + 8 * g) : zero8;
   }
 
-  // K and V tile rows (tid / 8) + 32 i, 16-byte chunk tid % 8: per-thread
-  // sources of tile 0, advanced by one tile per step
-  bf16x8 kreg[2], vreg[2];
-  const bf16* ksrc[2];
-  const bf16* vsrc[2];
+  // Tile t into LDS buffer buf: wave w moves the 8-row blocks w, w + NW, ...
+  // of both tiles; lane l fills row 8 * block + l / 8, granule slot l % 8.
+  auto dma = [&](int t, int buf) {
+    const int rows_left = it.s1 - (it.s0 + t * BN);
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int r = (tid >> 3) + 32 * i, ch = tid & 7;
-    ksrc[i] = K + (int64_t)(it.s0 + r) * p.k_ts + ch * 8;
-    vsrc[i] = Vt + r * p.vt_ds + ch * 8;
-  }
-  const int64_t kstep = (int64_t)BN * p.k_ts;
-  auto gload = [&](int t) {
-    const int rows_left = it.s1 - (it.s0 + t * BN);  // keys of this tile that exist
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int r = (tid >> 3) + 32 * i;
-      kreg[i] = r < rows_left ? *(const bf16x8*)(ksrc[i] + t * kstep) : zero8;
-      vreg[i] = *(const bf16x8*)(vsrc[i] + t * BN);
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int r = (tid >> 3) + 32 * i, ch = tid & 7;
-      *(bf16x8*)&Ks[buf][r * D + ((ch ^ lds_swz8(r)) * 8)] = kreg[i];
-      const int hp = ch >> 1, a = ch & 1;
-      const bf16x4 lo = {vreg[i][0], vreg[i][1], vreg[i][2], vreg[i][3]};
-      const bf16x4 hi = {vreg[i][4], vreg[i][5], vreg[i][6], vreg[i][7]};
-      *(bf16x4*)&Vs[buf][r * BN + (((2 * hp) ^ lds_swz8(r)) * 8) + 4 * a] = lo;
-      *(bf16x4*)&Vs[buf][r * BN + (((2 * hp + 1) ^ lds_swz8(r)) * 8) + 4 * a] = hi;
+    for (int j = 0; j < 8 / NW; ++j) {
+      const int rb = 8 * (wave + NW * j);
+      const int r = rb + (lane >> 3), ch = (lane & 7) ^ lds_swz8(r);
+      const int q4 = (r >> 2) & 3;
+      const int key = (r & ~15) | ((q4 == 1 ? 2 : (q4 == 2 ? 1 : q4)) << 2) | (r & 3);
+      const int kr = key < rows_left ? key : 0;  // rows past the end: any existing key (their scores are masked)
+      __builtin_amdgcn_global_load_lds((const void*)(K + (int64_t)(it.s0 + t * BN + kr) * p.k_ts + ch * 8),
+                                       (__attribute__((address_space(3))) void*)&Ks[buf][rb * D], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(Vt + (int64_t)r * p.vt_ds + t * BN + ch * 8),
+                                       (__attribute__((address_space(3))) void*)&Vs[buf][rb * BN], 16, 0, 0);
     }
   };
 
@@ -151,60 +188,76 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
   const float c2 = p.scale_log2;
   const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
 
-  gload(0);
-  lstore(0);
+  dma(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
 
-  // One key tile; MASKED is set only for the final, partial tile of a
-  // sequence, so full tiles carry no key-bound checks.
-  auto tile = [&](int t, auto masked) {
-    constexpr bool MASKED = decltype(masked)::value;
+  // One key tile.  MASKED is set only for the final, partial tile of a
+  // sequence, so full tiles carry no key-bound checks; FIRST only for the
+  // first tile.  Both take the exact step on every query block.
+  auto tile = [&](int t, auto masked, auto first) {
+    constexpr bool MASKED = decltype(masked)::value, FIRST = decltype(first)::value;
+    constexpr bool EXACT = MASKED || FIRST;
     const int kt = it.s0 + t * BN, buf = t & 1;
-    if (t + 1 < ntiles) gload(t + 1);
 
-    // Phase 1: scores of every query block (K fragments live only here).
+    bf16x8 kf[2][4];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int r = kb * 32 + r32;
+        kf[kb][c] = *(const bf16x8*)&Ks[buf][r * D + (((2 * c + g) ^ lds_swz8(r)) * 8)];
+      }
     f32x16 s[QB][2];
-    {
-      bf16x8 kf[2][4];
+    bf16x8 pb[QB][2][2];
+    bf16x8 vf[2][2][2];
+    auto score = [&](int qb) {
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+        s[qb][kb] = f32x16{};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[qb][kb] = mfma_bf16(kf[kb][c], qf[qb][c], s[qb][kb]);
+      }
+    };
+    auto pv = [&](int qb) {
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) oacc[qb][db] = mfma_bf16(vf[db][kb][h], pb[qb][kb][h], oacc[qb][db]);
+    };
+    auto probs = [&](int qb, const f32x16& a, const f32x16& b) {
+      const float mc = m_run[qb] * c2;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+        const f32x16& x = kb ? b : a;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) pb[qb][kb][i >> 3][i & 7] = f2bf(fast_exp2(__builtin_fmaf(x[i], c2, -mc)));
+      }
+    };
+    auto rowsum = [&](int qb) {
+      f32x4 r = {};
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int r = kb * 32 + r32;
-          kf[kb][c] = *(const bf16x8*)&Ks[buf][r * D + (((2 * c + g) ^ lds_swz8(r)) * 8)];
-        }
-#pragma unroll
-      for (int qb = 0; qb < QB; ++qb)
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-          s[qb][kb] = f32x16{};
-#pragma unroll
-          for (int c = 0; c < 4; ++c) s[qb][kb] = mfma_bf16(kf[kb][c], qf[qb][c], s[qb][kb]);
-        }
-    }
-
-    bf16x8 vf[2][2][2];  // V fragments, read just before the first P V product
-
-    // Phase 2 per query block: online softmax, probabilities packed as bf16
-    // PV operands, then O^T += V^T P^T.  The softmax of block qb runs on the
-    // vector ALU while the matrix core still works on the score MFMAs of
-    // later blocks or the P V MFMAs of block qb-1 (scheduling fences keep
-    // this order).
-#pragma unroll
-    for (int qb = 0; qb < QB; ++qb) {
-      if (QB > 1) __builtin_amdgcn_sched_barrier(0);
+        for (int h = 0; h < 2; ++h) r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sel8, pb[qb][kb][h], r, 0, 0, 0);
+      return r[0];
+    };
+    // exact step: mask, row maximum, move m (rescaling O and l), probabilities
+    auto exact = [&](int qb, f32x16& a, f32x16& b, auto is_first) {
       if (MASKED) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int key = kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3);
-            if (key >= it.s1) s[qb][kb][i] = -INFINITY;
-          }
+          for (int i = 0; i < 16; ++i)
+            if (kt + kb * 32 + 16 * (i >> 3) + 8 * g + (i & 7) >= it.s1) (kb ? b : a)[i] = -INFINITY;
       }
-      const float mx = lane_swap_max(max32(s[qb][0], s[qb][1]));
-      const float m_new = __builtin_fmaxf(m_run[qb], mx);
-      if (__any(m_new > m_run[qb])) {
+      const float mx = lane_swap_max(max32(a, b));
+      if (decltype(is_first)::value) {
+        m_run[qb] = mx;  // O and l are still zero
+      } else {
+        const float m_new = __builtin_fmaxf(m_run[qb], mx);
         const float alpha = fast_exp2((m_run[qb] - m_new) * c2);
         l_run[qb] *= alpha;
 #pragma unroll
@@ -214,18 +267,24 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
         }
         m_run[qb] = m_new;
       }
-      const float mc = m_new * c2;
-      float ls = 0.f;
-      bf16x8 pb[2][2];
+      probs(qb, a, b);
+    };
+
+    score(0);
 #pragma unroll
-      for (int kb = 0; kb < 2; ++kb)
+    for (int qb = 0; qb < QB; ++qb) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (qb + 1 < QB) score(qb + 1);
+      if (qb >= 1) pv(qb - 1);
+      if (EXACT) exact(qb, s[qb][0], s[qb][1], first);
+      else probs(qb, s[qb][0], s[qb][1]);
+      if (!EXACT && QB > 1) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const float e = fast_exp2(__builtin_fmaf(s[qb][kb][i], c2, -mc));
-          ls += e;
-          pb[kb][i >> 3][i & 7] = f2bf(e);
+        for (int j = 0; j < 8; ++j) {
+          __builtin_amdgcn_sched_group_barrier(0x002, 10, 0);  // VALU
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
         }
-      l_run[qb] += ls;
+      }
       if (qb == 0) {
 #pragma unroll
         for (int db = 0; db < 2; ++db)
@@ -236,31 +295,49 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
               const int d = db * 32 + r32;
               vf[db][kb][h] = *(const bf16x8*)&Vs[buf][d * BN + (((2 * (2 * kb + h) + g) ^ lds_swz8(d)) * 8)];
             }
+        // every LDS read of this tile's fragments is issued: move the next tile in
+        if (t + 1 < ntiles) dma(t + 1, buf ^ 1);
       }
-      if (QB > 1) __builtin_amdgcn_sched_barrier(0);
+      float ls = rowsum(qb);
+      if (!EXACT && __any(abs_bits_at_least(ls, __float_as_uint(kLazyBound)))) {
+        f32x16 r[2];
 #pragma unroll
-      for (int db = 0; db < 2; ++db)
+        for (int kb = 0; kb < 2; ++kb) {
+          r[kb] = f32x16{};
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
-#pragma unroll
-          for (int h = 0; h < 2; ++h) oacc[qb][db] = mfma_bf16(vf[db][kb][h], pb[kb][h], oacc[qb][db]);
+          for (int c = 0; c < 4; ++c) {
+            const int rr = kb * 32 + r32;
+            const bf16x8 k8 = *(const volatile bf16x8*)&Ks[buf][rr * D + (((2 * c + g) ^ lds_swz8(rr)) * 8)];
+            r[kb] = mfma_bf16(k8, qf[qb][c], r[kb]);
+          }
+        }
+        exact(qb, r[0], r[1], std::false_type{});
+        ls = rowsum(qb);
+      }
+      l_run[qb] += ls;
     }
-    if (QB > 1) __builtin_amdgcn_sched_barrier(0);
-
+    __builtin_amdgcn_sched_barrier(0);
+    pv(QB - 1);
+    __builtin_amdgcn_sched_barrier(0);
     if (t + 1 < ntiles) {
-      lstore(buf ^ 1);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
     }
   };
   const bool ragged = (it.s1 - it.s0) % BN != 0;
   const int nfull = ntiles - (ragged ? 1 : 0);
-  for (int t = 0; t < nfull; ++t) tile(t, std::false_type{});
-  if (ragged) tile(ntiles - 1, std::true_type{});
+  if (nfull > 0) tile(0, std::false_type{}, std::true_type{});
+  for (int t = 1; t < nfull; ++t) tile(t, std::false_type{}, std::false_type{});
+  if (ragged) {
+    if (ntiles == 1)
+      tile(0, std::true_type{}, std::true_type{});
+    else
+      tile(ntiles - 1, std::true_type{}, std::false_type{});
+  }
 
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
-    const float lt = l_run[qb] + __shfl_xor(l_run[qb], 32);
-    const float inv = 1.f / lt;
+    const float inv = 1.f / l_run[qb];
     const int row = it.q0 + (wave * QB + qb) * 32 + r32;
     if (row < it.s1) {
 #pragma unroll
@@ -268,17 +345,263 @@ __global__ __launch_bounds__(256, OCC) void attn_bf16_kernel(AttnParams p) {
 #pragma unroll
         for (int i = 0; i < 16; i += 4) {
           const int d = db * 32 + 8 * (i >> 2) + 4 * g;
-          if (OUT_F32) {
-            float* o = (float*)p.o + row * p.o_ts + head * p.o_hs + d;
-            const f32x4 v = {oacc[qb][db][i] * inv, oacc[qb][db][i + 1] * inv, oacc[qb][db][i + 2] * inv,
-                             oacc[qb][db][i + 3] * inv};
-            *(f32x4*)o = v;
-          } else {
-            bf16* o = (bf16*)p.o + row * p.o_ts + head * p.o_hs + d;
-            const bf16x4 v = {f2bf(oacc[qb][db][i] * inv), f2bf(oacc[qb][db][i + 1] * inv),
-                              f2bf(oacc[qb][db][i + 2] * inv), f2bf(oacc[qb][db][i + 3] * inv)};
-            *(bf16x4*)o = v;
+          bf16* o = (bf16*)p.o + row * p.o_ts + head * p.o_hs + d;
+          const bf16x4 v = {f2bf(oacc[qb][db][i] * inv), f2bf(oacc[qb][db][i + 1] * inv),
+                            f2bf(oacc[qb][db][i + 2] * inv), f2bf(oacc[qb][db][i + 3] * inv)};
+          *(bf16x4*)o = v;
+        }
+    }
+  }
+}
+
+// ============================================================== BF16-score, FP8 P V kernel
+//
+// Global attention with the scores in bfloat16 (Q K^T exactly as in
+// attn_bf16_kernel) and the P V product on OCP E4M3 operands: probabilities
+// and V codes, with V's per-128-row-block power-of-two scales entering the
+// scaled f8f6f4 MFMA as E8M0 operands (relative to the head's largest V
+// scale, vmax, as in attn_fp8_kernel).  The E4M3 rounding of Q and K, which
+// moves logits of order 10 by several percent, is avoided; P and V are the
+// only operands rounded to 3 mantissa bits.
+//
+// K tile rows are permuted so that lane group g of the score MFMA ends up
+// with the 32 consecutive keys 32 g .. 32 g + 31 of the tile (register i of
+// score block kb holds key 32 g + 16 kb + i): LDS row 32 kb + r holds key
+// 32 ((r >> 2) & 1) + 16 kb + 4 (r >> 3) + (r & 3).  The 32 probabilities of
+// a lane then form, in key order, the lane's B operand of the 32x32x64 E4M3
+// MFMA, and the V^T tile (64 d rows of 64 one-byte keys, 16-byte granules
+// swizzled with lds_swz4) is read in key order.
+//
+// Probabilities: p = 2^(c2 s - c2 m + log2(448) - 2), i.e. the row maximum is
+// placed two binades below 448 when m moves; later full tiles skip the
+// maximum search and convert against the current m.  A score that rose more
+// than about two binades above the placed maximum converts to the E4M3 NaN
+// code (the hardware conversion returns NaN above 464); the row-sum MFMA
+// (16x16x128 with the lane selector, over the same E4M3 codes as the P V
+// product) turns that into a NaN sum, which is tested on its bits, and only
+// then is the exact step taken (scores recomputed from the K tile in LDS,
+// maximum, rescale of O and l, new m).  The first and the partial last tile
+// always take the exact step.  O = vmax * sum_j p8_j (s_v(j) / vmax) V8_j /
+// sum_j p8_j, a convex combination of the decoded value rows.
+template <int QB, int NW, int OCC>
+__global__ __launch_bounds__(64 * NW, OCC) void attn_fp8pv_kernel(AttnParams p) {
+  constexpr int BN = 64, D = kHeadDim, BM = 32 * QB * NW;
+  constexpr float kPlace = 8.80735492205760410745f - 2.f;  // log2(448) - 2 binades of headroom
+  __shared__ __attribute__((aligned(16))) bf16 Ks[2][BN * D];
+  __shared__ __attribute__((aligned(16))) uint8_t Vs[2][D * BN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 5, r32 = lane & 31;
+  const int head = blockIdx.y;
+  const Item it = resolve_item(p.seqs, blockIdx.x, BM);
+
+  const bf16* Q = (const bf16*)p.q + head * p.q_hs;
+  const bf16* K = (const bf16*)p.k + head * p.k_hs;
+  const uint8_t* Vt = (const uint8_t*)p.vt + head * p.vt_hs + it.vb;
+  const i32x2* KI = (const i32x2*)(p.kinfo + 2 * (head * p.sc_hs + it.bb));
+  const float vmax = p.vmax[head];
+
+  const bf16x8 zero8 = {};
+  const int sel4 = (((lane >> 2) ^ (lane >> 4)) & 1) ? 0 : 0x38383838;  // row-sum selector: E4M3 1.0 or 0
+  const i32x8 sel8 = {sel4, sel4, sel4, sel4, sel4, sel4, sel4, sel4};
+  bf16x8 qf[QB][4];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const int row = it.q0 + (wave * QB + qb) * 32 + r32;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      qf[qb][c] = row < it.s1 ? *(const bf16x8*)(Q + row * p.q_ts + 16 * c + 8 * g) : zero8;
+  }
+
+  // Tile t into LDS buffer buf.  K: 8 blocks of 8 rows x 128 bytes; V^T: 4
+  // blocks of 16 rows x 64 bytes; wave w moves K blocks w, w + NW, ... and V
+  // blocks w, w + NW, ... (lane l: K row 8 b + l / 8, slot l % 8; V row
+  // 16 b + l / 4, slot l % 4).
+  auto dma = [&](int t, int buf) {
+    const int rows_left = it.s1 - (it.s0 + t * BN);
+#pragma unroll
+    for (int j = 0; j < 8 / NW; ++j) {
+      const int rb = 8 * (wave + NW * j);
+      const int R = rb + (lane >> 3), ch = (lane & 7) ^ lds_swz8(R);
+      const int r = R & 31;
+      const int key = 32 * ((r >> 2) & 1) + 16 * (R >> 5) + 4 * (r >> 3) + (r & 3);
+      const int kr = key < rows_left ? key : 0;  // rows past the end: any existing key (their scores are masked)
+      __builtin_amdgcn_global_load_lds((const void*)(K + (int64_t)(it.s0 + t * BN + kr) * p.k_ts + ch * 8),
+                                       (__attribute__((address_space(3))) void*)&Ks[buf][rb * D], 16, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < (4 + NW - 1) / NW; ++j) {
+      const int vb = wave + NW * j;
+      if (vb < 4) {
+        const int d = 16 * vb + (lane >> 2), ch = (lane & 3) ^ lds_swz4(d);
+        __builtin_amdgcn_global_load_lds((const void*)(Vt + (int64_t)d * p.vt_ds + t * BN + ch * 16),
+                                         (__attribute__((address_space(3))) void*)&Vs[buf][16 * vb * BN], 16, 0, 0);
+      }
+    }
+  };
+
+  f32x16 oacc[QB][2];
+  float m_run[QB], l_run[QB];
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    oacc[qb][0] = f32x16{};
+    oacc[qb][1] = f32x16{};
+    m_run[qb] = -INFINITY;
+    l_run[qb] = 0.f;
+  }
+  const float c2 = p.scale_log2;
+  const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
+
+  dma(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+
+  auto tile = [&](int t, auto masked, auto first) {
+    constexpr bool MASKED = decltype(masked)::value, FIRST = decltype(first)::value;
+    constexpr bool EXACT = MASKED || FIRST;
+    const int kt = it.s0 + t * BN, buf = t & 1;
+    const int ev = KI[(kt - it.s0) / kQuantRows][1];  // E8M0 code of this key block's V scale / vmax
+
+    bf16x8 kf[2][4];
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int r = kb * 32 + r32;
+        kf[kb][c] = *(const bf16x8*)&Ks[buf][r * D + (((2 * c + g) ^ lds_swz8(r)) * 8)];
+      }
+    f32x16 s[QB][2];
+    i32x8 pw[QB];
+    i32x8 vf[2];
+    auto score = [&](int qb) {
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+        s[qb][kb] = f32x16{};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[qb][kb] = mfma_bf16(kf[kb][c], qf[qb][c], s[qb][kb]);
+      }
+    };
+    auto pv = [&](int qb) {
+      oacc[qb][0] = mfma_fp8_scaled(vf[0], pw[qb], oacc[qb][0], ev, 127);
+      oacc[qb][1] = mfma_fp8_scaled(vf[1], pw[qb], oacc[qb][1], ev, 127);
+    };
+    // E4M3 probabilities of one query block, in key order (32 per lane)
+    auto probs = [&](int qb, const f32x16& a, const f32x16& b) {
+      const float mc = m_run[qb] * c2 - kPlace;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb) {
+        const f32x16& x = kb ? b : a;
+#pragma unroll
+        for (int i = 0; i < 16; i += 4)
+          pw[qb][(16 * kb + i) >> 2] = pack_e4m3x4(fast_exp2(__builtin_fmaf(x[i], c2, -mc)),
+                                                   fast_exp2(__builtin_fmaf(x[i + 1], c2, -mc)),
+                                                   fast_exp2(__builtin_fmaf(x[i + 2], c2, -mc)),
+                                                   fast_exp2(__builtin_fmaf(x[i + 3], c2, -mc)));
+      }
+    };
+    auto rowsum = [&](int qb) { return mfma_fp8_16(sel8, pw[qb], f32x4{})[0]; };
+    auto exact = [&](int qb, f32x16& a, f32x16& b, auto is_first) {
+      if (MASKED) {
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (kt + 32 * g + 16 * kb + i >= it.s1) (kb ? b : a)[i] = -INFINITY;
+      }
+      const float mx = lane_swap_max(max32(a, b));
+      if (decltype(is_first)::value) {
+        m_run[qb] = mx;  // O and l are still zero
+      } else {
+        const float m_new = __builtin_fmaxf(m_run[qb], mx);
+        const float alpha = fast_exp2((m_run[qb] - m_new) * c2);
+        l_run[qb] *= alpha;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          oacc[qb][0][i] *= alpha;
+          oacc[qb][1][i] *= alpha;
+        }
+        m_run[qb] = m_new;
+      }
+      probs(qb, a, b);
+    };
+
+    score(0);
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+      __builtin_amdgcn_sched_barrier(0);
+      if (qb + 1 < QB) score(qb + 1);
+      if (qb >= 1) pv(qb - 1);
+      if (EXACT) exact(qb, s[qb][0], s[qb][1], first);
+      else probs(qb, s[qb][0], s[qb][1]);
+      if (!EXACT && QB > 1) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);  // VALU
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+        }
+      }
+      if (qb == 0) {
+#pragma unroll
+        for (int db = 0; db < 2; ++db) {
+          const int d = db * 32 + r32, sw = lds_swz4(d);
+          const i32x4 lo = *(const i32x4*)&Vs[buf][d * BN + (((2 * g) ^ sw) * 16)];
+          const i32x4 hi = *(const i32x4*)&Vs[buf][d * BN + (((2 * g + 1) ^ sw) * 16)];
+          vf[db] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+        }
+        // every LDS read of this tile's fragments is issued: move the next tile in
+        if (t + 1 < ntiles) dma(t + 1, buf ^ 1);
+      }
+      float ls = rowsum(qb);
+      if (!EXACT && __any(abs_bits_at_least(ls, 0x7f800000u))) {
+        f32x16 r[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb) {
+          r[kb] = f32x16{};
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int rr = kb * 32 + r32;
+            const bf16x8 k8 = *(const volatile bf16x8*)&Ks[buf][rr * D + (((2 * c + g) ^ lds_swz8(rr)) * 8)];
+            r[kb] = mfma_bf16(k8, qf[qb][c], r[kb]);
           }
+        }
+        exact(qb, r[0], r[1], std::false_type{});
+        ls = rowsum(qb);
+      }
+      l_run[qb] += ls;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    pv(QB - 1);
+    __builtin_amdgcn_sched_barrier(0);
+    if (t + 1 < ntiles) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+    }
+  };
+  const bool ragged = (it.s1 - it.s0) % BN != 0;
+  const int nfull = ntiles - (ragged ? 1 : 0);
+  if (nfull > 0) tile(0, std::false_type{}, std::true_type{});
+  for (int t = 1; t < nfull; ++t) tile(t, std::false_type{}, std::false_type{});
+  if (ragged) {
+    if (ntiles == 1)
+      tile(0, std::true_type{}, std::true_type{});
+    else
+      tile(ntiles - 1, std::true_type{}, std::false_type{});
+  }
+
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+    const float inv = vmax / l_run[qb];
+    const int row = it.q0 + (wave * QB + qb) * 32 + r32;
+    if (row < it.s1) {
+#pragma unroll
+      for (int db = 0; db < 2; ++db)
+#pragma unroll
+        for (int i = 0; i < 16; i += 4) {
+          const int d = db * 32 + 8 * (i >> 2) + 4 * g;
+          bf16* o = (bf16*)p.o + row * p.o_ts + head * p.o_hs + d;
+          const bf16x4 v = {f2bf(oacc[qb][db][i] * inv), f2bf(oacc[qb][db][i + 1] * inv),
+                            f2bf(oacc[qb][db][i + 2] * inv), f2bf(oacc[qb][db][i + 3] * inv)};
+          *(bf16x4*)o = v;
         }
     }
   }
@@ -391,17 +714,6 @@ __global__ __launch_bounds__(256, 1) void attn_f32_kernel(AttnParams p) {
 
 
 // ============================================================== FP8 kernel
-// E4M3 conversion without a clamp: the hardware rounds to nearest even, so
-// values up to 464 give 448 and larger ones give the NaN code, which the
-// kernel below uses as its overflow signal.  Four floats -> four E4M3 codes
-// in one dword (bytes in argument order).  The first conversion fills the
-// low half (its high half is scratch), the second writes the high half in
-// place.
-__device__ __forceinline__ int pack_e4m3x4(float e0, float e1, float e2, float e3) {
-  const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(e0, e1, __float_as_int(e0), false);
-  return __builtin_amdgcn_cvt_pk_fp8_f32(e2, e3, lo, true);
-}
-
 // E4M3 probabilities 2^x of one 32-query x 64-key score block, packed as the
 // B operand of the P V product.
 __device__ __forceinline__ i32x8 probs(const f32x16& a, const f32x16& b) {
@@ -647,7 +959,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
       // NaN code makes the row sum NaN (tested on the bits, not with a float
       // compare: this file is built without NaN semantics), and only then
       // are the scores recomputed from the K tile in LDS for the exact step
-      if (!EXACT && __any((__float_as_uint(lsum[0]) & 0x7fffffffu) >= 0x7f800000u)) {
+      if (!EXACT && __any(abs_bits_at_least(lsum[0], 0x7f800000u))) {
         f32x16 r[2];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
@@ -857,7 +1169,7 @@ __global__ void scale_max_kernel(const float* sk, const float* sv, int64_t sc_hs
 struct AttnVariant {
   int qb, nw, occ;
 };
-static const AttnVariant kBf16Variants[] = {{1, 4, 2}, {2, 4, 2}};
+static const AttnVariant kBf16Variants[] = {{1, 4, 2}, {2, 4, 2}, {1, 8, 2}};
 static const AttnVariant kFp8Variants[] = {{1, 4, 2}, {2, 4, 2}, {1, 8, 2}, {2, 8, 2}};
 constexpr int kNumBf16Variants = sizeof(kBf16Variants) / sizeof(kBf16Variants[0]);
 constexpr int kNumFp8Variants = sizeof(kFp8Variants) / sizeof(kFp8Variants[0]);
@@ -876,19 +1188,25 @@ int attn_block_rows(int prec, int variant) {
   return 128;
 }
 
-template <bool OUT_F32>
-static void launch_bf16_variant(const AttnParams& p, dim3 grid, int variant, hipStream_t s) {
-  switch (variant) {
-    case 1: hipLaunchKernelGGL((attn_bf16_kernel<2, OUT_F32, 2>), grid, dim3(256), 0, s, p); break;
-    default: hipLaunchKernelGGL((attn_bf16_kernel<1, OUT_F32, 2>), grid, dim3(256), 0, s, p); break;
-  }
-}
-
-hipError_t launch_attn_bf16(const AttnParams& p, int H, int variant, bool out_f32, hipStream_t s) {
+hipError_t launch_attn_bf16(const AttnParams& p, int H, int variant, hipStream_t s) {
   if (variant < 0 || variant >= kNumBf16Variants) return hipErrorInvalidValue;
   const dim3 grid(p.n_items, H);
-  if (out_f32) launch_bf16_variant<true>(p, grid, variant, s);
-  else launch_bf16_variant<false>(p, grid, variant, s);
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((attn_bf16_kernel<2, 4, 2>), grid, dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL((attn_bf16_kernel<1, 8, 2>), grid, dim3(512), 0, s, p); break;
+    default: hipLaunchKernelGGL((attn_bf16_kernel<1, 4, 2>), grid, dim3(256), 0, s, p); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_attn_fp8pv(const AttnParams& p, int H, int variant, hipStream_t s) {
+  if (variant < 0 || variant >= kNumBf16Variants) return hipErrorInvalidValue;
+  const dim3 grid(p.n_items, H);
+  switch (variant) {
+    case 1: hipLaunchKernelGGL((attn_fp8pv_kernel<2, 4, 2>), grid, dim3(256), 0, s, p); break;
+    case 2: hipLaunchKernelGGL((attn_fp8pv_kernel<1, 8, 2>), grid, dim3(512), 0, s, p); break;
+    default: hipLaunchKernelGGL((attn_fp8pv_kernel<1, 4, 2>), grid, dim3(256), 0, s, p); break;
+  }
   return hipGetLastError();
 }
 

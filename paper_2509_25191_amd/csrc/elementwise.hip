@@ -68,6 +68,37 @@ hipError_t launch_layernorm(const float* x, int64_t ldx, const void* g, const vo
                  : ln_dispatch<float>(x, ldx, g, b, eps, h, ldh, rows, C, s);
 }
 
+// Row statistics in the layout the fused LayerNorm consumes: for every row
+// and every 128-column slice t, (mean_t, M2_t) = (mean of the slice, sum of
+// squared deviations from it), two passes over the slice in float32.  One
+// wave per row, two values per lane per slice.  The RESID epilogue of the
+// projection GEMMs produces the same statistics for the rows it updates; this
+// kernel covers residual streams that no epilogue wrote (the aggregator's
+// input tokens, the front end's embedded tokens).
+__global__ __launch_bounds__(256) void row_stats_kernel(const float* x, int64_t ldx, int rows, int C, float* stats) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const float* xr = x + (int64_t)row * ldx;
+  const int nt = C / 128;
+  for (int t = 0; t < nt; ++t) {
+    const float a = xr[128 * t + 2 * lane], b = xr[128 * t + 2 * lane + 1];
+    const float mean = wave_sum(a + b) * (1.f / 128.f);
+    const float m2 = wave_sum((a - mean) * (a - mean) + (b - mean) * (b - mean));
+    if (lane == 0) {
+      stats[((int64_t)row * nt + t) * 2] = mean;
+      stats[((int64_t)row * nt + t) * 2 + 1] = m2;
+    }
+  }
+}
+
+hipError_t launch_row_stats(const float* x, int64_t ldx, int rows, int C, float* stats, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  if (C % 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(row_stats_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, x, ldx, rows, C, stats);
+  return hipGetLastError();
+}
+
 // Seeded synthetic bfloat16 values for the autotuner: a counter-based hash
 // (SplitMix64 finaliser) of (seed, index) mapped to a uniform value in
 // [-scale, scale).

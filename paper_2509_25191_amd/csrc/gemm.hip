@@ -64,11 +64,12 @@ __device__ __forceinline__ void epi4(const GemmParams& p, int r, int col, float 
   } else if (EPI == EPI_RESID) {
     float* x = p.x + grow * p.ldx + col;
     const f32x4 old = *(const f32x4*)x;
-    float nv[4] = {old[0] + v[0], old[1] + v[1], old[2] + v[2], old[3] + v[3]};
-    st4<float>(x, nv);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] += old[j];  // the new residual, also returned to the caller
+    st4<float>(x, v);
     if (p.out) {
-      if (p.out_f32) st4<float>((float*)p.out + grow * p.ldo + col, nv);
-      else st4<bf16>((bf16*)p.out + grow * p.ldo + col, nv);
+      if (p.out_f32) st4<float>((float*)p.out + grow * p.ldo + col, v);
+      else st4<bf16>((bf16*)p.out + grow * p.ldo + col, v);
     }
   } else if (EPI == EPI_EMBED) {
     const int64_t f = grow / p.emb_np;
@@ -87,12 +88,21 @@ __device__ __forceinline__ void epi4(const GemmParams& p, int r, int col, float 
   }
 }
 
+// Sum over the 32 lanes of a half wave (lanes l and l ^ o for o < 32).
+__device__ __forceinline__ float half_wave_sum(float v) {
+#pragma unroll
+  for (int o = 16; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
 // ------------------------------------------------------------------ BF16 MFMA
 // 128 x 128 output tile, BK = 64, 4 waves in a 2 x 2 grid of 64 x 64 wave
 // tiles (2 x 2 MFMA 32x32x16 blocks each).  A and W tiles are staged in LDS
 // with 16-byte granules XOR-swizzled by row; the accumulators go through LDS
 // once more so that the epilogue reads and writes whole rows.
-template <int EPI>
+// LNA: A is LayerNorm(x), normalised from float32 rows while its tile is
+// loaded (the LayerNorm output is never stored).
+template <int EPI, bool LNA>
 __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
   constexpr int BM = 128, BN = 128, BK = 64, CLD = BN + 4;
   __shared__ __attribute__((aligned(16))) char smem[BM * CLD * 4];
@@ -108,14 +118,61 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
   const bf16* W = (const bf16*)p.w;
   const bf16x8 zero8 = {};
 
-  bf16x8 areg[4], wreg[4];
-  auto gload = [&](int k0) {
+  // LNA: mean and 1/sqrt(var + eps) of the thread's 4 A rows, from the
+  // (mean, M2) pairs of their 128-column slices (Chan's combination; every
+  // slice has 128 values)
+  float ln_mu[4], ln_rs[4];
+  if (LNA) {
+    const int nt = p.K / 128;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int r = (tid >> 3) + 32 * i, ch = tid & 7;
-      const bf16* a = p.a_hs ? A + (k0 >> 6) * p.a_hs + (int64_t)(m0 + r) * kHeadDim + ch * 8
-                             : A + (int64_t)(m0 + r) * p.lda + k0 + ch * 8;
-      areg[i] = (m0 + r < p.M) ? *(const bf16x8*)a : zero8;
+      const int r = (tid >> 3) + 32 * i;
+      ln_mu[i] = 0.f;
+      ln_rs[i] = 0.f;
+      if (m0 + r < p.M) {
+        const float* st = p.stats + ((int64_t)p.row0 + m0 + r) * nt * 2;
+        float mu = 0.f;
+        for (int t = 0; t < nt; ++t) mu += st[2 * t];
+        mu /= (float)nt;
+        float m2 = 0.f;
+        for (int t = 0; t < nt; ++t) {
+          const float d = st[2 * t] - mu;
+          m2 += st[2 * t + 1] + 128.f * d * d;
+        }
+        ln_mu[i] = mu;
+        ln_rs[i] = 1.f / __builtin_sqrtf(m2 / (float)p.K + p.ln_eps);
+      }
+    }
+  }
+  bf16x8 areg[4], wreg[4];
+  auto gload = [&](int k0) {
+    const int ch = tid & 7;
+    bf16x8 gam, bet;
+    if (LNA) {
+      gam = *(const bf16x8*)((const bf16*)p.ln_g + k0 + ch * 8);
+      bet = *(const bf16x8*)((const bf16*)p.ln_b + k0 + ch * 8);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = (tid >> 3) + 32 * i;
+      if (LNA) {
+        bf16x8 h = zero8;
+        if (m0 + r < p.M) {
+          const float* xa = (const float*)p.a + (int64_t)(m0 + r) * p.lda + k0 + ch * 8;
+          const f32x4 lo = *(const f32x4*)xa, hi = *(const f32x4*)(xa + 4);
+          const float nm = -ln_mu[i] * ln_rs[i];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const float xv = j < 4 ? lo[j] : hi[j - 4];
+            h[j] = f2bf(__builtin_fmaf(__builtin_fmaf(xv, ln_rs[i], nm), bf2f(gam[j]), bf2f(bet[j])));
+          }
+        }
+        areg[i] = h;
+      } else {
+        const bf16* a = p.a_hs ? A + (k0 >> 6) * p.a_hs + (int64_t)(m0 + r) * kHeadDim + ch * 8
+                               : A + (int64_t)(m0 + r) * p.lda + k0 + ch * 8;
+        areg[i] = (m0 + r < p.M) ? *(const bf16x8*)a : zero8;
+      }
       wreg[i] = *(const bf16x8*)(W + (int64_t)(n0 + r) * p.K + k0 + ch * 8);
     }
   };
@@ -174,12 +231,27 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
         Cs[row * CLD + col] = acc[mi][nj][i];
       }
   __syncthreads();
+  // the 32 lanes of a half wave share one row (idx / 32)
   for (int idx = tid; idx < BM * (BN / 4); idx += 256) {
     const int row = idx / (BN / 4), c4 = (idx % (BN / 4)) * 4;
-    if (m0 + row >= p.M) continue;
+    const bool valid = m0 + row < p.M;
     const f32x4 cv = *(const f32x4*)&Cs[row * CLD + c4];
     float v[4] = {cv[0], cv[1], cv[2], cv[3]};
-    epi4<EPI, bf16>(p, m0 + row, n0 + c4, v);
+    if (valid) epi4<EPI, bf16>(p, m0 + row, n0 + c4, v);
+    if (EPI == EPI_RESID && p.stats) {
+      // (mean, M2) of the new residual over this tile's 128 columns, two passes
+      const float mean = half_wave_sum(v[0] + v[1] + v[2] + v[3]) * (1.f / BN);
+      float q = 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) q += (v[j] - mean) * (v[j] - mean);
+      q = half_wave_sum(q);
+      if (valid && (tid & 31) == 0) {
+        const int nt = p.N / BN;
+        float* st = p.stats + (((int64_t)p.row0 + m0 + row) * nt + n0 / BN) * 2;
+        st[0] = mean;
+        st[1] = q;
+      }
+    }
   }
 }
 
@@ -229,16 +301,25 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmParams p) {
 
 hipError_t launch_gemm_bf16(const GemmParams& p, Epi epi, hipStream_t s) {
   dim3 grid(p.N / 128, (p.M + 127) / 128), block(256);
+  const bool ln = p.ln_g != nullptr;
+  if (ln && (epi != EPI_QKV && epi != EPI_GELU)) return hipErrorInvalidValue;
   switch (epi) {
-    case EPI_QKV: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_QKV>, grid, block, 0, s, p); break;
-    case EPI_RESID: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_RESID>, grid, block, 0, s, p); break;
-    case EPI_GELU: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_GELU>, grid, block, 0, s, p); break;
-    case EPI_EMBED: hipLaunchKernelGGL(gemm_bf16_kernel<EPI_EMBED>, grid, block, 0, s, p); break;
+    case EPI_QKV:
+      if (ln) hipLaunchKernelGGL((gemm_bf16_kernel<EPI_QKV, true>), grid, block, 0, s, p);
+      else hipLaunchKernelGGL((gemm_bf16_kernel<EPI_QKV, false>), grid, block, 0, s, p);
+      break;
+    case EPI_RESID: hipLaunchKernelGGL((gemm_bf16_kernel<EPI_RESID, false>), grid, block, 0, s, p); break;
+    case EPI_GELU:
+      if (ln) hipLaunchKernelGGL((gemm_bf16_kernel<EPI_GELU, true>), grid, block, 0, s, p);
+      else hipLaunchKernelGGL((gemm_bf16_kernel<EPI_GELU, false>), grid, block, 0, s, p);
+      break;
+    case EPI_EMBED: hipLaunchKernelGGL((gemm_bf16_kernel<EPI_EMBED, false>), grid, block, 0, s, p); break;
   }
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_f32(const GemmParams& p, Epi epi, hipStream_t s) {
+  if (p.ln_g || p.stats) return hipErrorInvalidValue;  // the float32 path runs its LayerNorms separately
   dim3 grid(p.N / 64, (p.M + 63) / 64), block(256);
   switch (epi) {
     case EPI_QKV: hipLaunchKernelGGL(gemm_f32_kernel<EPI_QKV>, grid, block, 0, s, p); break;

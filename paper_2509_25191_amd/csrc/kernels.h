@@ -40,7 +40,10 @@ struct AttnParams {
 };
 
 // ---- attention (attention.hip)
-hipError_t launch_attn_bf16(const AttnParams& p, int H, int variant, bool out_f32, hipStream_t s);
+// BF16 variants: (query blocks of 32 rows per wave, waves) 0 = (1, 4), 1 = (2, 4), 2 = (1, 8)
+hipError_t launch_attn_bf16(const AttnParams& p, int H, int variant, hipStream_t s);
+// Global attention with bfloat16 scores and E4M3 P V (same tile variants as BF16)
+hipError_t launch_attn_fp8pv(const AttnParams& p, int H, int variant, hipStream_t s);
 hipError_t launch_attn_f32(const AttnParams& p, int H, hipStream_t s);
 // FP8 variants: 0 = (1 query block per wave, 4 waves), 1 = (2, 4), 2 = (1, 8), 3 = (2, 8)
 hipError_t launch_attn_fp8(const AttnParams& p, int H, int variant, hipStream_t s);
@@ -84,6 +87,14 @@ struct GemmParams {
   void* out; int64_t ldo; int out_f32;
   // EPI_GELU: hid[r, c] = gelu(result)
   void* hid; int64_t ldh;
+  // Fused LayerNorm.  ln_g != null: A is LayerNorm(x) computed while the A
+  // tile is loaded: a (float32, leading dimension lda) holds the residual rows
+  // and stats the (mean, M2) pairs of their C/128 128-column slices (rows
+  // indexed from row0), combined per row into the mean and the biased
+  // variance; A(m, k) = (a(m, k) - mean) / sqrt(var + ln_eps) * ln_g[k] + ln_b[k].
+  // EPI_RESID with stats != null: the epilogue writes those pairs for the
+  // rows it updates (slice n0 / 128 of the output tile).
+  float* stats; const void* ln_g; const void* ln_b; float ln_eps;
   // EPI_EMBED: A row m is patch i = m % emb_np of frame f = m / emb_np;
   // x[f * emb_pd + kEmbedSpecial + i, c] = result + pos[1 + i, c] (pos [.., N], bias type)
   const void* pos; int emb_np, emb_pd;
@@ -96,6 +107,8 @@ hipError_t launch_gemm_f32(const GemmParams& p, Epi epi, hipStream_t s);
 hipError_t launch_layernorm(const float* x, int64_t ldx, const void* g, const void* b, float eps, void* h,
                             int64_t ldh, int rows, int C, bool bf16_io, hipStream_t s);
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
+// Per-row (mean, M2) of every 128-column slice of x [rows, C] -> stats [rows, C / 128, 2]
+hipError_t launch_row_stats(const float* x, int64_t ldx, int rows, int C, float* stats, hipStream_t s);
 
 // ---- patch-embedding front end (embed.hip)
 constexpr int kEmbedPatch = 14;                          // patch side in pixels

@@ -256,7 +256,8 @@ struct Ws {
   void* v = nullptr;         // F32: [H, N, D]; BF16 / FP8: [H, rows, D] staging of V before its transposition
   bf16* vt = nullptr;        // BF16 / FP8: transposed V [H, D, vt_cols] (FP8: frame chunks only)
   void* o = nullptr;         // FP8: global attention output [H, N, D] bf16
-  void* h = nullptr;         // LayerNorm output [rows, C]
+  void* h = nullptr;         // F32: LayerNorm output [rows, C] (BF16 / FP8 normalise inside the GEMMs)
+  float* stats = nullptr;    // BF16 / FP8: per row and 128-column slice of x, (mean, M2) [N, C / 128, 2]
   void* hid = nullptr;       // MLP hidden [rows, F]
   uint8_t* q8 = nullptr;     // FP8 codes [H, N, D]
   uint8_t* k8 = nullptr;
@@ -289,7 +290,7 @@ Ws carve(const vggtx_config& c, const WsShape& sh, vggtx_prec prec, char* base) 
   const int64_t N = sh.n_tokens, C = c.dim, F = c.mlp_hidden, R = sh.rows, H = c.heads;
   const size_t el = prec == VGGTX_F32 ? 4 : 2;
   if (sh.with_x) w.x = (float*)take(N * C * 4);
-  if (prec == VGGTX_FP8_E4M3) {
+  if (prec == VGGTX_FP8_E4M3) {  // Q, K live only as E4M3 codes beyond one row range
     w.q = take(R * C * 2);
     w.k = take(R * C * 2);
   } else {
@@ -298,15 +299,18 @@ Ws carve(const vggtx_config& c, const WsShape& sh, vggtx_prec prec, char* base) 
   }
   w.v = take((prec == VGGTX_F32 ? N : R) * C * el);
   if (prec != VGGTX_F32) w.vt = (bf16*)take(C * sh.vt_cols * 2);
-  w.h = take(R * C * el);
+  if (prec == VGGTX_F32) w.h = take(R * C * 4);
+  else w.stats = (float*)take(N * (C / 128) * 2 * 4);
   w.hid = take(R * F * el);
   if (prec == VGGTX_FP8_E4M3) {
     w.o = take(N * C * 2);
     w.q8 = (uint8_t*)take(N * C);
     w.k8 = (uint8_t*)take(N * C);
-    w.v8t = (uint8_t*)take(C * sh.npad);
     w.sq = (float*)take(H * sh.nblk * 4);
     w.sk = (float*)take(H * sh.nblk * 4);
+  }
+  if (prec == VGGTX_FP8_E4M3 || prec == VGGTX_FP8_PV) {
+    w.v8t = (uint8_t*)take(C * sh.npad);
     w.sv = (float*)take(H * sh.nblk * 4);
     w.vmax = (float*)take(H * 4);
     w.kinfo = (int*)take(H * sh.nblk * 8);
@@ -331,7 +335,8 @@ vggtx_status check_cfg(const vggtx_config* c) {
 }
 
 vggtx_status check_prec(vggtx_prec p) {
-  if (p != VGGTX_F32 && p != VGGTX_BF16 && p != VGGTX_FP8_E4M3) return fail(VGGTX_E_INVALID, "unknown precision %d", (int)p);
+  if (p != VGGTX_F32 && p != VGGTX_BF16 && p != VGGTX_FP8_E4M3 && p != VGGTX_FP8_PV)
+    return fail(VGGTX_E_INVALID, "unknown precision %d", (int)p);
   return VGGTX_OK;
 }
 vggtx_status check_block_w(const vggtx_block_w& w, const char* what, int layer) {
@@ -385,16 +390,20 @@ vggtx_status out_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, i
   g.M = M; g.N = C; g.K = C;
   g.row0 = (int)r0;
   g.x = br.ws.x; g.ldx = C;
+  g.stats = br.ws.stats;  // LN2 statistics of the updated rows (BF16 / FP8)
   {
     Span sp(br.ctx, VGGTX_K_GEMM, 2.0 * M * C * C, br.stream);
     VGGTX_HIP(gemm(g, EPI_RESID, br.stream));
   }
-  {
-    Span sp(br.ctx, VGGTX_K_OTHER, 0.0, br.stream);
-    VGGTX_HIP(launch_layernorm(br.ws.x + r0 * C, C, w.ln2_g, w.ln2_b, c.ln_eps, br.ws.h, C, M, C, lp, br.stream));
-  }
   memset(&g, 0, sizeof(g));
-  g.a = br.ws.h; g.lda = C;
+  if (lp) {  // LN2 applied while the fc1 GEMM loads x
+    g.a = br.ws.x + r0 * C; g.lda = C;
+    g.stats = br.ws.stats; g.ln_g = w.ln2_g; g.ln_b = w.ln2_b; g.ln_eps = c.ln_eps;
+  } else {
+    Span sp(br.ctx, VGGTX_K_OTHER, 0.0, br.stream);
+    VGGTX_HIP(launch_layernorm(br.ws.x + r0 * C, C, w.ln2_g, w.ln2_b, c.ln_eps, br.ws.h, C, M, C, false, br.stream));
+    g.a = br.ws.h; g.lda = C;
+  }
   g.w = w.w_fc1; g.bias = w.b_fc1;
   g.M = M; g.N = F; g.K = C;
   g.row0 = (int)r0;
@@ -410,6 +419,7 @@ vggtx_status out_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, i
   g.row0 = (int)r0;
   g.x = br.ws.x; g.ldx = C;
   g.out = out; g.ldo = ldo; g.out_f32 = out_f32 ? 1 : 0;
+  g.stats = br.ws.stats;  // statistics for the next block's LN1
   {
     Span sp(br.ctx, VGGTX_K_GEMM, 2.0 * M * C * F, br.stream);
     VGGTX_HIP(gemm(g, EPI_RESID, br.stream));
@@ -424,13 +434,16 @@ vggtx_status qkv_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, i
   const int C = c.dim;
   const bool lp = lowp(br.prec);
   const int M = (int)(r1 - r0);
-  {
-    Span sp(br.ctx, VGGTX_K_OTHER, 0.0, br.stream);
-    VGGTX_HIP(launch_layernorm(br.ws.x + r0 * C, C, w.ln1_g, w.ln1_b, c.ln_eps, br.ws.h, C, M, C, lp, br.stream));
-  }
   GemmParams g;
   memset(&g, 0, sizeof(g));
-  g.a = br.ws.h; g.lda = C;
+  if (lp) {  // LN1 applied while the GEMM loads x, from the statistics the last epilogue left
+    g.a = br.ws.x + r0 * C; g.lda = C;
+    g.stats = br.ws.stats; g.ln_g = w.ln1_g; g.ln_b = w.ln1_b; g.ln_eps = c.ln_eps;
+  } else {
+    Span sp(br.ctx, VGGTX_K_OTHER, 0.0, br.stream);
+    VGGTX_HIP(launch_layernorm(br.ws.x + r0 * C, C, w.ln1_g, w.ln1_b, c.ln_eps, br.ws.h, C, M, C, false, br.stream));
+    g.a = br.ws.h; g.lda = C;
+  }
   g.w = w.w_qkv; g.bias = w.b_qkv;
   g.M = M; g.N = 3 * C; g.K = C;
   g.row0 = (int)r0;
@@ -440,6 +453,15 @@ vggtx_status qkv_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, i
   g.q_scale = 1.f;
   Span sp(br.ctx, VGGTX_K_GEMM, 2.0 * M * 3 * C * C, br.stream);
   VGGTX_HIP((lp ? launch_gemm_bf16 : launch_gemm_f32)(g, EPI_QKV, br.stream));
+  return VGGTX_OK;
+}
+
+// (mean, M2) statistics of the residual rows [0, N) for the fused LayerNorm,
+// where no epilogue has produced them (BF16 / FP8 only).
+vggtx_status seed_stats(const BlockRun& br) {
+  if (!lowp(br.prec)) return VGGTX_OK;
+  Span sp(br.ctx, VGGTX_K_OTHER, 0.0, br.stream);
+  VGGTX_HIP(launch_row_stats(br.ws.x, br.ctx->cfg.dim, (int)br.N, br.ctx->cfg.dim, br.ws.stats, br.stream));
   return VGGTX_OK;
 }
 
@@ -508,7 +530,27 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
     for (auto& tn : make_tables(s, attn_block_rows(1, var))) {
       p.seqs = tn.first; p.n_items = tn.second;
       Span sp(ctx, cls, table_flops(tn.first, H), st);
-      VGGTX_HIP(launch_attn_bf16(p, H, var, false, st));
+      VGGTX_HIP(launch_attn_bf16(p, H, var, st));
+    }
+    return VGGTX_OK;
+  }
+  if (prec == VGGTX_FP8_PV) {
+    {
+      Span sp(ctx, VGGTX_K_OTHER, 0.0, st);
+      if (!io.prepared)
+        for (auto& tn : make_tables(s, kQuantRows))
+          VGGTX_HIP(launch_quant_fp8((const bf16*)io.v, io.v_ts, io.v_hs, 1.f, io.v8t, (int64_t)kHeadDim * io.npad,
+                                     io.npad, true, 0, io.sv, io.nblk, tn.first, tn.second, H, st));
+      // the K-scale half of kinfo is unused by this kernel
+      VGGTX_HIP(launch_scale_max(io.sv, io.sv, io.nblk, (int)s.scale_blocks(), io.vmax, io.kinfo, H, st));
+    }
+    p.vt = io.v8t;
+    p.sv = io.sv; p.sc_hs = io.nblk; p.vmax = io.vmax; p.kinfo = io.kinfo;
+    const int var = ctx->bf16_variant;
+    for (auto& tn : make_tables(s, attn_block_rows(1, var))) {
+      p.seqs = tn.first; p.n_items = tn.second;
+      Span sp(ctx, cls, table_flops(tn.first, H), st);
+      VGGTX_HIP(launch_attn_fp8pv(p, H, var, st));
     }
     return VGGTX_OK;
   }
@@ -600,7 +642,8 @@ vggtx_status block_global(const BlockRun& br, const vggtx_block_w& w, const Seqs
   const int H = c.heads;
   const int64_t N = br.N, R = br.sh.rows;
   const size_t el = lowp(br.prec) ? 2 : 4;
-  const bool fp8 = br.prec == VGGTX_FP8_E4M3;
+  const bool fp8 = br.prec == VGGTX_FP8_E4M3;     // Q, K, V as E4M3 codes
+  const bool fp8pv = br.prec == VGGTX_FP8_PV;     // V as E4M3 codes, Q and K bfloat16
   const std::vector<Piece> pieces = make_pieces(seqs, R);
   const HView q{br.ws.q, (fp8 ? R : N) * kHeadDim}, k{br.ws.k, (fp8 ? R : N) * kHeadDim};
   const HView v{br.ws.v, (br.prec == VGGTX_F32 ? N : R) * kHeadDim};
@@ -614,6 +657,11 @@ vggtx_status block_global(const BlockRun& br, const vggtx_block_w& w, const Seqs
       const auto tn = piece_table(pc, 64);
       VGGTX_HIP(launch_v_transpose_bf16((const bf16*)v.p, kHeadDim, v.hs, br.ws.vt, kHeadDim * br.sh.vt_cols,
                                         br.sh.vt_cols, tn.first, tn.second, H, st));
+    } else if (fp8pv) {
+      Span sp(br.ctx, VGGTX_K_OTHER, 0.0, st);
+      const auto tn = piece_table(pc, kQuantRows);
+      VGGTX_HIP(launch_quant_fp8((const bf16*)v.p, kHeadDim, v.hs, 1.f, br.ws.v8t, kHeadDim * br.sh.npad, br.sh.npad,
+                                 true, 0, br.ws.sv, br.sh.nblk, tn.first, tn.second, H, st));
     } else if (fp8) {
       Span sp(br.ctx, VGGTX_K_OTHER, 0.0, st);
       const auto tn = piece_table(pc, kQuantRows);
@@ -639,7 +687,7 @@ vggtx_status block_global(const BlockRun& br, const vggtx_block_w& w, const Seqs
   io.vt = br.ws.vt;
   io.q8 = br.ws.q8; io.k8 = br.ws.k8; io.v8t = br.ws.v8t;
   io.sq = br.ws.sq; io.sk = br.ws.sk; io.sv = br.ws.sv; io.vmax = br.ws.vmax; io.kinfo = br.ws.kinfo;
-  io.npad = fp8 ? br.sh.npad : br.sh.vt_cols;
+  io.npad = fp8 || fp8pv ? br.sh.npad : br.sh.vt_cols;
   io.nblk = br.sh.nblk;
   io.n_tokens = N;
   io.prepared = true;
@@ -679,7 +727,7 @@ vggtx_status block_frames(const BlockRun& br, const vggtx_block_w& w, int S, int
     io.npad = br.sh.vt_cols;
     io.n_tokens = r1 - r0;
     VGGTX_TRY(run_attention(br.ctx, VGGTX_K_ATTN_FRAME, io, fr, c.heads,
-                            br.prec == VGGTX_F32 ? VGGTX_F32 : VGGTX_BF16, br.stream));
+                            br.prec == VGGTX_F32 ? VGGTX_F32 : VGGTX_BF16, br.stream));  // FP8 modes: frames in BF16
     VGGTX_TRY(out_phase(br, w, r0, r1, qc, out, ldo, out_f32));
   }
   return VGGTX_OK;
@@ -716,8 +764,9 @@ WsShape agg_shape(const vggtx_config& c, int64_t total_frames, int P, vggtx_prec
   sh.n_tokens = total_frames * P;
   sh.rows = std::max<int64_t>(kQuantRows, std::min<int64_t>(total_frames, c.frame_chunk) * P);
   const int64_t ppad = round_up(P, kKeyPad);
-  // FP8: vt serves the frame chunks only (global attention reads v8t)
-  sh.vt_cols = (prec == VGGTX_FP8_E4M3 ? std::min<int64_t>(total_frames, c.frame_chunk) : total_frames) * ppad;
+  // FP8 / FP8_PV: vt serves the frame chunks only (global attention reads v8t)
+  sh.vt_cols = (prec == VGGTX_FP8_E4M3 || prec == VGGTX_FP8_PV ? std::min<int64_t>(total_frames, c.frame_chunk)
+                                                                  : total_frames) * ppad;
   sh.npad = total_frames * ppad;
   sh.nblk = total_frames * cdiv(P, kQuantRows);
   sh.with_x = with_x;
@@ -771,6 +820,7 @@ vggtx_status aggregate_impl(vggtx_handle h, const float* tokens, const int32_t* 
     br.ws.x = const_cast<float*>(tokens);  // the caller handed the buffer over (vggtx_config.tokens_inplace)
   else
     VGGTX_HIP(launch_copy_f32(tokens, br.ws.x, N * C, br.stream));
+  VGGTX_TRY(seed_stats(br));
   const Seqs scenes = seqs_from_offsets(frame_offsets, n_scenes, P);
   const bool out_f32 = out_dtype == VGGTX_OUT_F32;
   const size_t oel = out_f32 ? 4 : 2;
@@ -806,9 +856,11 @@ Ws carve_attn(int H, int64_t N, int64_t npad, int64_t nblk, vggtx_prec prec, cha
   if (prec == VGGTX_FP8_E4M3) {
     w.q8 = (uint8_t*)take(N * C);
     w.k8 = (uint8_t*)take(N * C);
-    w.v8t = (uint8_t*)take(C * npad);
     w.sq = (float*)take(H * nblk * 4);
     w.sk = (float*)take(H * nblk * 4);
+  }
+  if (prec == VGGTX_FP8_E4M3 || prec == VGGTX_FP8_PV) {
+    w.v8t = (uint8_t*)take(C * npad);
     w.sv = (float*)take(H * nblk * 4);
     w.vmax = (float*)take(H * 4);
     w.kinfo = (int*)take(H * nblk * 8);
@@ -914,7 +966,7 @@ vggtx_status embed_impl(vggtx_handle h, const float* images, int height, int wid
   VGGTX_TRY(check_image_shape(height, width));
   VGGTX_TRY(check_embed_w(w));
   const vggtx_config& c = h->cfg;
-  const vggtx_prec pr = prec == VGGTX_FP8_E4M3 ? VGGTX_BF16 : prec;
+  const vggtx_prec pr = prec == VGGTX_FP8_E4M3 || prec == VGGTX_FP8_PV ? VGGTX_BF16 : prec;
   const int64_t S = frame_offsets[n_scenes];
   const EmbedPlan need = embed_plan(c, S, height, width, pr, nullptr);
   if (S * need.Pd > kMaxTokens) return fail(VGGTX_E_UNSUPPORTED, "%lld tokens exceed the supported %lld",
@@ -964,6 +1016,7 @@ vggtx_status embed_impl(vggtx_handle h, const float* images, int height, int wid
       Span sp(h, VGGTX_K_GEMM, 2.0 * g.M * C * kEmbedK, st);
       VGGTX_HIP((lp ? launch_gemm_bf16 : launch_gemm_f32)(g, EPI_EMBED, st));
     }
+    VGGTX_TRY(seed_stats(br));
     for (int l = 0; l < w->depth; ++l)
       VGGTX_TRY(block_frames(br, w->blocks[l], nf, e.Pd, nf, nullptr, 0, false));
     FirstMask fm;
@@ -1222,6 +1275,7 @@ vggtx_status vggtx_block(vggtx_handle h, const float* x_in, float* x_out, const 
   br.N = N;
   br.stream = (hipStream_t)stream;
   if (x_in != x_out) VGGTX_HIP(launch_copy_f32(x_in, x_out, N * c.dim, br.stream));
+  VGGTX_TRY(seed_stats(br));
   const Seqs s = seqs_from_offsets(seq_offsets, n_seq, 1);
   return block_global(br, *w, s, nullptr, 0, false);
 }
@@ -1232,7 +1286,7 @@ vggtx_status vggtx_embed_workspace_size(vggtx_handle h, int total_frames, int he
   VGGTX_TRY(check_prec(prec));
   VGGTX_TRY(check_image_shape(height, width));
   if (total_frames < 0) return fail(VGGTX_E_INVALID, "frames %d", total_frames);
-  const vggtx_prec pr = prec == VGGTX_FP8_E4M3 ? VGGTX_BF16 : prec;
+  const vggtx_prec pr = prec == VGGTX_FP8_E4M3 || prec == VGGTX_FP8_PV ? VGGTX_BF16 : prec;
   *bytes = embed_plan(h->cfg, total_frames, height, width, pr, nullptr).total;
   return VGGTX_OK;
 }
@@ -1354,7 +1408,8 @@ vggtx_status vggtx_attn_workspace_size(vggtx_handle h, const int32_t* seq_offset
 vggtx_status vggtx_attn_frame(vggtx_handle h, const void* q, const void* k, const void* v, void* o, int S, int P, int H,
                               int D, vggtx_layout in_layout, vggtx_layout out_layout, vggtx_prec prec, void* ws,
                               size_t ws_bytes, void* stream) {
-  if (prec == VGGTX_FP8_E4M3) return fail(VGGTX_E_UNSUPPORTED, "frame attention runs in float32 or bfloat16");
+  if (prec == VGGTX_FP8_E4M3 || prec == VGGTX_FP8_PV)
+    return fail(VGGTX_E_UNSUPPORTED, "frame attention runs in float32 or bfloat16");
   if (S < 0 || P < 0) return fail(VGGTX_E_INVALID, "S = %d, P = %d", S, P);
   Seqs s;
   s.uniform = true; s.first = 0; s.len = P; s.n = (P > 0) ? S : 0; s.first_index = 0;

@@ -13,7 +13,7 @@ from typing import Dict, List, Optional, Sequence
 import torch
 
 __all__ = [
-    "F32", "BF16", "FP8_E4M3", "OUT_F32", "OUT_BF16", "VggtxError", "library_path", "load",
+    "F32", "BF16", "FP8_E4M3", "FP8_PV", "OUT_F32", "OUT_BF16", "VggtxError", "library_path", "load",
     "Config", "BlockW", "PairW", "Layout", "Handle", "create", "destroy", "workspace_size",
     "aggregate", "aggregate_varlen", "block", "attn_workspace_size", "attn_frame", "attn_global",
     "quantize_fp8", "status_str", "last_error", "BLOCK_FIELDS", "timing_enable", "timing_read", "timing_poll",
@@ -23,7 +23,7 @@ __all__ = [
     "K_ATTN_GLOBAL", "K_ATTN_FRAME", "K_GEMM", "K_OTHER",
 ]
 
-F32, BF16, FP8_E4M3 = 0, 1, 2
+F32, BF16, FP8_E4M3, FP8_PV = 0, 1, 2, 3
 K_ATTN_GLOBAL, K_ATTN_FRAME, K_GEMM, K_OTHER = 0, 1, 2, 3
 OUT_F32, OUT_BF16 = 0, 1
 BLOCK_FIELDS = ("ln1_g", "ln1_b", "w_qkv", "b_qkv", "w_o", "b_o",

@@ -25,7 +25,7 @@ def _dt(prec):
     return torch.float32 if prec == vg.F32 else torch.bfloat16
 
 
-@pytest.mark.parametrize("prec,tol", [(vg.F32, 1e-4), (vg.BF16, 2e-2), (vg.FP8_E4M3, 6e-2)])
+@pytest.mark.parametrize("prec,tol", [(vg.F32, 1e-4), (vg.BF16, 2e-2), (vg.FP8_E4M3, 6e-2), (vg.FP8_PV, 6e-2)])
 @pytest.mark.parametrize("std", [0.02, 0.15])
 def test_block_parity(prec, tol, std):
     m = SMALL
@@ -53,7 +53,8 @@ def test_block_parity(prec, tol, std):
 
 
 @pytest.mark.parametrize("prec,tol,out_dtype", [(vg.F32, 1e-4, vg.OUT_F32), (vg.BF16, 2e-2, vg.OUT_BF16),
-                                                (vg.BF16, 2e-2, vg.OUT_F32), (vg.FP8_E4M3, 6e-2, vg.OUT_BF16)])
+                                                (vg.BF16, 2e-2, vg.OUT_F32), (vg.FP8_E4M3, 6e-2, vg.OUT_BF16),
+                                                (vg.FP8_PV, 6e-2, vg.OUT_F32)])
 def test_aggregate_one_pair_s8(prec, tol, out_dtype):
     """One frame/global pair, C=256, S=8 frames of P=86 tokens, seed 0."""
     m = SMALL
@@ -91,7 +92,7 @@ def test_chunking_is_bitwise_invariant():
         assert torch.equal(o, outs[0])
 
 
-@pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3])
+@pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3, vg.FP8_PV])
 def test_chunking_is_bitwise_invariant_varlen(prec):
     """Three scenes of 2, 3 and 2 frames of 86 tokens: frame chunks of 1, 3,
     7 and 128 frames also change the scene-aligned pieces of the global
@@ -105,7 +106,7 @@ def test_chunking_is_bitwise_invariant_varlen(prec):
         assert torch.equal(o, outs[0])
 
 
-@pytest.mark.parametrize("prec", [vg.BF16, vg.FP8_E4M3])
+@pytest.mark.parametrize("prec", [vg.BF16, vg.FP8_E4M3, vg.FP8_PV])
 def test_tokens_inplace_equals_copy(prec):
     """With tokens_inplace the forward runs in the caller's tokens buffer:
     the same outputs bit for bit, a workspace smaller by S*P*C*4 bytes, and

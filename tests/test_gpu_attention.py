@@ -13,7 +13,7 @@ from gpu_util import DEV, max_abs_rel, to_dev, head_major_to_tokens
 vg = pytest.importorskip("paper_2509_25191_amd.vggtx")
 pytestmark = pytest.mark.gpu
 
-TOL = {vg.F32: 1e-4, vg.BF16: 2e-2, vg.FP8_E4M3: 6e-2}
+TOL = {vg.F32: 1e-4, vg.BF16: 2e-2, vg.FP8_E4M3: 6e-2, vg.FP8_PV: 6e-2}
 
 
 @pytest.fixture(scope="module")
@@ -111,13 +111,9 @@ def test_attn_global_single_key_tails(handle, prec):
     assert e < TOL[prec]
 
 
-@pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3])
-def test_attn_global_first_tile_far_below_max(handle, prec):
-    """The first 128 keys of each sequence (two key tiles, one FP8 scale
-    block) point against every query (logits near -96, i.e. -138 in base 2)
-    and the later keys give ordinary logits: the first tiles' weights vanish
-    against the row maximum found later, with no overflow in the streamed
-    rescale on the way."""
+def _far_below_case():
+    """Sequences whose first 128 keys point against every query (logits near
+    -96, -138 in base 2) before ordinary keys follow."""
     H, D = 2, 64
     offs = [0, 300, 520]
     rng = np.random.default_rng(41)
@@ -129,6 +125,37 @@ def test_attn_global_first_tile_far_below_max(handle, prec):
     for a in offs[:-1]:
         k[:, a:a + 128] = -48.0 * u + rng.normal(0, 0.05, (H, 128, D))
     v = rng.normal(0, 1, (H, n, D))
+    return q, k, v, offs
+
+
+def _rising_case():
+    """Keys that line up with the queries more and more: every 64-key tile
+    raises the row maximum by 3 binades in one sequence and by 1.2 in the
+    other."""
+    H, D = 2, 64
+    offs = [0, 900, 1500]
+    rng = np.random.default_rng(43)
+    u = rng.normal(0, 1, (H, 1, D))
+    u /= np.linalg.norm(u, axis=-1, keepdims=True)
+    n = offs[-1]
+    q = 8.0 * u + rng.normal(0, 0.05, (H, n, D))
+    k = np.empty((H, n, D))
+    for (a, b), step in zip(zip(offs[:-1], offs[1:]), (3.0, 1.2)):
+        tile = (np.arange(b - a) // 64)[None, :, None]
+        # q.k / sqrt(D) = level in natural units, i.e. step * tile binades
+        k[:, a:b] = (step * np.log(2.0)) * tile * u + rng.normal(0, 0.05, (H, b - a, D))
+    v = rng.normal(0, 1, (H, n, D))
+    return q, k, v, offs
+
+
+@pytest.mark.parametrize("prec", [vg.F32, vg.BF16, vg.FP8_E4M3])
+def test_attn_global_first_tile_far_below_max(handle, prec):
+    """The first 128 keys of each sequence (two key tiles, one FP8 scale
+    block) point against every query (logits near -96, i.e. -138 in base 2)
+    and the later keys give ordinary logits: the first tiles' weights vanish
+    against the row maximum found later, with no overflow in the streamed
+    rescale on the way."""
+    q, k, v, offs = _far_below_case()
     if prec != vg.F32:
         q, k, v = (synth.round_bf16(x.astype(np.float32)) for x in (q, k, v))
     got = _run_global(handle, q, k, v, offs, prec)
@@ -162,19 +189,8 @@ def test_attn_global_rising_maximum(handle, prec):
     recompute-and-rescale path.  FP8 is compared with the oracle on the
     E4M3-rounded Q, K and V, so that only the rounding of the probabilities
     and the rescaling are measured."""
-    H, D = 2, 64
-    offs = [0, 900, 1500]
-    rng = np.random.default_rng(43)
-    u = rng.normal(0, 1, (H, 1, D))
-    u /= np.linalg.norm(u, axis=-1, keepdims=True)
-    n = offs[-1]
-    q = 8.0 * u + rng.normal(0, 0.05, (H, n, D))
-    k = np.empty((H, n, D))
-    for (a, b), step in zip(zip(offs[:-1], offs[1:]), (3.0, 1.2)):
-        tile = (np.arange(b - a) // 64)[None, :, None]
-        # q.k / sqrt(D) = level in natural units, i.e. step * tile binades
-        k[:, a:b] = (step * np.log(2.0)) * tile * u + rng.normal(0, 0.05, (H, b - a, D))
-    v = rng.normal(0, 1, (H, n, D))
+    q, k, v, offs = _rising_case()
+    D = q.shape[-1]
     if prec != vg.F32:
         q, k, v = (synth.round_bf16(x.astype(np.float32)) for x in (q, k, v))
     got = _run_global(handle, q, k, v, offs, prec)
@@ -279,7 +295,7 @@ def _handle_with(env):
 
 
 @pytest.mark.parametrize("prec,key,values", [(vg.FP8_E4M3, "VGGTX_FP8_VARIANT", [0, 1, 2, 3]),
-                                             (vg.BF16, "VGGTX_BF16_VARIANT", [0, 1])])
+                                             (vg.BF16, "VGGTX_BF16_VARIANT", [0, 1, 2])])
 def test_tile_variants_are_bitwise_identical(prec, key, values):
     """Every tile variant computes each query row with the same arithmetic in the same order."""
     H, D = 16, 64
@@ -304,7 +320,7 @@ def test_autotune_picks_a_variant_and_caches_it(tmp_path, monkeypatch):
     h = vg.Handle(0, dim=1024, heads=16, mlp_hidden=4096)
     v8 = vg.autotune(h.h, vg.FP8_E4M3, n_tokens=8192)
     vb = vg.autotune(h.h, vg.BF16, n_tokens=8192)
-    assert 0 <= v8 < 4 and 0 <= vb < 2
+    assert 0 <= v8 < 4 and 0 <= vb < 3
     lines = cache.read_text().split()
     assert len(lines) == 8  # two records of (arch, prec, variant, ms)
     # a second handle reuses the cached choice without timing
@@ -358,3 +374,48 @@ def test_attn_global_fp8_streamed_placement_diagnostic(handle, case):
             emu[:, a:b] = attention_fp8_streamed(q[:, a:b], k[:, a:b], v[:, a:b])[0]
     print(f"fp8 kernel vs its placement-rule emulation, {case}: max_abs_rel={max_abs_rel(got, emu):.3e}")
     assert np.isfinite(got).all()
+
+
+@pytest.mark.parametrize("case", ["R0", "R1", "R2", "varlen", "tails", "far_below", "rising"])
+def test_attn_global_fp8pv_meets_fp8_gate(handle, case):
+    """Scores in bfloat16, P and V in E4M3 (VGGTX_FP8_PV): within the FP8
+    gate of the float64 definition in every logit regime, since Q and K keep
+    8 mantissa bits (their E4M3 rounding is what moves large logits), on
+    ragged and one-key tails, and through the overflow fallback of the
+    probability placement (keys rising 3 and 1.2 binades per tile, a first
+    tile far below the row maximum)."""
+    if case in ("R0", "R1", "R2"):
+        q, k, v = _qkv(4, 8 * 86, 64, case, seed=1, frames=8)
+        offs = [0, 8 * 86]
+    elif case == "varlen":
+        offs = [0, 200, 201, 201, 718, 845]
+        q, k, v = _qkv(4, offs[-1], 64, "R1", seed=2)
+    elif case == "tails":
+        offs = [0, 65, 194, 387]
+        q, k, v = _qkv(4, offs[-1], 64, "R0", seed=10)
+    else:
+        q, k, v, offs = _far_below_case() if case == "far_below" else _rising_case()
+        q, k, v = (synth.round_bf16(x.astype(np.float32)) for x in (q, k, v))
+    got = _run_global(handle, q, k, v, offs, vg.FP8_PV)
+    ref = _oracle_seqs(q, k, v, offs)
+    e = max_abs_rel(got, ref)
+    print(f"fp8pv {case}: max_abs_rel={e:.3e}")
+    assert np.isfinite(got).all() and e < TOL[vg.FP8_PV]
+
+
+@pytest.mark.parametrize("key,values", [("VGGTX_BF16_VARIANT", [0, 1, 2])])
+def test_fp8pv_tile_variants_are_bitwise_identical(key, values):
+    H, D = 16, 64
+    offs = [0, 700, 701, 1500, 3100]
+    q, k, v = _qkv(H, offs[-1], D, "R1", seed=8)
+    qd, kd, vd = (_dev_tokens(a, vg.FP8_PV) for a in (q, k, v))
+    outs = []
+    for val in values:
+        h = _handle_with({key: val})
+        o = torch.zeros_like(qd)
+        vg.attn_global(h.h, qd, kd, vd, o, offs, vg.FP8_PV)
+        torch.cuda.synchronize()
+        outs.append(o)
+        h.close()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])

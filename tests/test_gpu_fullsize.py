@@ -98,7 +98,7 @@ def _e2e_problem():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec,tol", [(vg.BF16, 2e-2), (vg.FP8_E4M3, 6e-2)])
+@pytest.mark.parametrize("prec,tol", [(vg.BF16, 2e-2), (vg.FP8_E4M3, 6e-2), (vg.FP8_PV, 6e-2)])
 def test_aggregate_vggt_l_depth24_end_to_end(prec, tol):
     """All 24 layers at C=1024, H=16, F=4096, P=1374, S=2, with no teacher
     forcing: the GPU output of layers 4/11/17/23 against the FP64 forward."""
@@ -184,7 +184,7 @@ def _check_rows(q, k, v, o, seq_start, seq_end, rows, heads):
     return max(errs)
 
 
-@pytest.mark.parametrize("prec,tol", [(vg.BF16, 2e-2), (vg.FP8_E4M3, 6e-2)])
+@pytest.mark.parametrize("prec,tol", [(vg.BF16, 2e-2), (vg.FP8_E4M3, 6e-2), (vg.FP8_PV, 6e-2)])
 def test_attn_global_s1000_sampled_rows(prec, tol):
     S, H = 1000, 16
     N = S * P
