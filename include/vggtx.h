@@ -72,6 +72,10 @@ typedef struct {
   int tokens_inplace; /* 1: vggtx_aggregate[_varlen] keep the residual stream in the caller's tokens
                          buffer (which must then be writable; it is overwritten) instead of a copy
                          in the workspace, whose size shrinks by S*P*C*4 bytes; 0: tokens are read only */
+  int attn_schedule;  /* global attention work distribution (BF16, FP8_PV, FP8_E4M3; results are the same):
+                         0: queue mode, as many workgroups as the GPU holds at once take (sequence, head,
+                         query tile) items from a work counter in the workspace, longest sequence first;
+                         1: one workgroup per item (plain grid) */
 } vggtx_config;
 
 /* Device pointers of one block's parameters: float32 for VGGTX_F32, bfloat16
@@ -134,6 +138,24 @@ vggtx_status vggtx_aggregate_varlen(vggtx_handle h, const float* tokens,
                                     const int32_t* out_layers, int n_out,
                                     void* out, vggtx_dtype out_dtype, vggtx_prec prec,
                                     void* ws, size_t ws_bytes, void* stream);
+
+/* Graph mode of vggtx_aggregate and vggtx_aggregate_varlen (Sec. 4.3 runs
+ * the same forward shape over many scenes; graphs remove its per-launch host
+ * cost).  With enable = 1, each call records its kernel launches on the host
+ * instead of enqueueing them and runs them as one HIP graph held by the
+ * handle: the first call of a given structure (the same kernels, launch
+ * shapes and argument sizes in order: same frame counts, P, layer list,
+ * precision and config) builds and instantiates the graph; later calls of
+ * that structure update the arguments of the nodes whose arguments changed
+ * (so reallocated tokens, weights, outputs or workspace are followed without
+ * a rebuild) and launch it on `stream`.  Results are bitwise those of direct
+ * calls.  At most 8 graphs are kept (least recently used evicted); enable = 0
+ * destroys them.  Kernel timing (vggtx_timing_enable) does not see graph
+ * launches.  Errors: VGGTX_E_INVALID for a null handle or enable not 0/1. */
+vggtx_status vggtx_graph_mode(vggtx_handle h, int enable);
+/* stats (host int64 [4]): graphs held, graphs built, node argument updates,
+ * graph launches, counted since the handle was created. */
+vggtx_status vggtx_graph_stats(vggtx_handle h, int64_t* stats);
 
 /* One transformer block (the unit both halves of a layer are made of) over
  * `n_seq` sequences back to back; token offsets host int32 [n_seq+1]

@@ -14,6 +14,8 @@
 // MFMA accumulator.  That makes the softmax statistics lane-local (plus one
 // exchange with lane l^32) and lets the probabilities feed the P V product
 // (O^T = V^T P^T) straight from registers.
+#include <stdint.h>
+
 #include <type_traits>
 
 #include "common.h"
@@ -49,6 +51,39 @@ __device__ __forceinline__ Item resolve_item(const SeqTable& t, int item, int ro
   return it;
 }
 
+// Work distribution.  Grid mode (p.queue null): workgroup (x, y) runs work
+// item x of head y.  Queue mode: the grid has one workgroup per (item, head)
+// in x, and each workgroup, when it starts, takes the next work index w from
+// the counter *p.queue (zero at launch), so items start in index order
+// whatever order the hardware dispatches workgroups in.  Indices run
+// sequence by sequence in the table's order (longest first for list tables),
+// head by head within a sequence: the longest items start first, the
+// shortest ones fill the tail, and the workgroups running together share the
+// K and V of one (sequence, head).
+__device__ __forceinline__ void take_work(const AttnParams& p, int* slot, int& head, int& item) {
+  if (!p.queue) {
+    head = blockIdx.y;
+    item = blockIdx.x;
+    return;
+  }
+  if (threadIdx.x == 0) *slot = atomicAdd(p.queue, 1);
+  __syncthreads();
+  const int w = __builtin_amdgcn_readfirstlane(*slot);  // uniform: keeps the item arithmetic scalar
+  const SeqTable& t = p.seqs;
+  if (t.uniform) {
+    head = w / p.n_items;
+    item = w - head * p.n_items;
+    return;
+  }
+  const int H = p.n_heads;
+  int seq = 0;
+  while (seq < t.n_seq - 1 && w >= H * t.tile_end[seq]) ++seq;
+  const int prev = seq ? t.tile_end[seq - 1] : 0;
+  const int n = t.tile_end[seq] - prev;
+  const int j = w - H * prev;
+  head = j / n;
+  item = prev + (j - head * n);
+}
 
 // max of 2 x 16 values as four chains of three-input maxima (v_max3_f32)
 __device__ __forceinline__ float max32(const f32x16& a, const f32x16& b) {
@@ -139,8 +174,10 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_bf16_kernel(AttnParams p) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 5, r32 = lane & 31;
-  const int head = blockIdx.y;
-  const Item it = resolve_item(p.seqs, blockIdx.x, BM);
+  __shared__ int s_work;
+  int head, item;
+  take_work(p, &s_work, head, item);
+  const Item it = resolve_item(p.seqs, item, BM);
 
   const bf16* Q = (const bf16*)p.q + head * p.q_hs;
   const bf16* K = (const bf16*)p.k + head * p.k_hs;
@@ -392,8 +429,10 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8pv_kernel(AttnParams p) 
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 5, r32 = lane & 31;
-  const int head = blockIdx.y;
-  const Item it = resolve_item(p.seqs, blockIdx.x, BM);
+  __shared__ int s_work;
+  int head, item;
+  take_work(p, &s_work, head, item);
+  const Item it = resolve_item(p.seqs, item, BM);
 
   const bf16* Q = (const bf16*)p.q + head * p.q_hs;
   const bf16* K = (const bf16*)p.k + head * p.k_hs;
@@ -779,8 +818,10 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 5, r32 = lane & 31;
-  const int head = blockIdx.y;
-  const Item it = resolve_item(p.seqs, blockIdx.x, BM);
+  __shared__ int s_work;
+  int head, item;
+  take_work(p, &s_work, head, item);
+  const Item it = resolve_item(p.seqs, item, BM);
   const uint8_t* Q = (const uint8_t*)p.q + head * p.q_hs;
   const uint8_t* K = (const uint8_t*)p.k + head * p.k_hs;
   const uint8_t* Vt = (const uint8_t*)p.vt + head * p.vt_hs + it.vb;
@@ -1188,64 +1229,72 @@ int attn_block_rows(int prec, int variant) {
   return 128;
 }
 
+__global__ void zero_i32_kernel(int* x, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0;
+}
+
+// Grid launch (workgroup (x, y) = item x of head y) or, with p.queue, the
+// counter reset and one workgroup per (item, head) in x, each taking its work
+// index from the counter (take_work).
+template <typename Kernel>
+static hipError_t launch_attn_kernel(Kernel kernel, const AttnParams& p, int H, int threads, hipStream_t s) {
+  if (p.n_items <= 0 || H <= 0) return hipSuccess;
+  if (!p.queue) return launch(kernel, dim3(p.n_items, H), dim3(threads), 0, s, p);
+  const int64_t n_work = (int64_t)H * p.n_items;
+  if (p.n_heads != H || n_work > INT32_MAX) return hipErrorInvalidValue;
+  const hipError_t e = launch(zero_i32_kernel, dim3(1), dim3(64), 0, s, p.queue, 1);
+  if (e != hipSuccess) return e;
+  return launch(kernel, dim3((unsigned)n_work), dim3(threads), 0, s, p);
+}
+
 hipError_t launch_attn_bf16(const AttnParams& p, int H, int variant, hipStream_t s) {
-  if (variant < 0 || variant >= kNumBf16Variants) return hipErrorInvalidValue;
-  const dim3 grid(p.n_items, H);
   switch (variant) {
-    case 1: hipLaunchKernelGGL((attn_bf16_kernel<2, 4, 2>), grid, dim3(256), 0, s, p); break;
-    case 2: hipLaunchKernelGGL((attn_bf16_kernel<1, 8, 2>), grid, dim3(512), 0, s, p); break;
-    default: hipLaunchKernelGGL((attn_bf16_kernel<1, 4, 2>), grid, dim3(256), 0, s, p); break;
+    case 0: return launch_attn_kernel(attn_bf16_kernel<1, 4, 2>, p, H, 256, s);
+    case 1: return launch_attn_kernel(attn_bf16_kernel<2, 4, 2>, p, H, 256, s);
+    case 2: return launch_attn_kernel(attn_bf16_kernel<1, 8, 2>, p, H, 512, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_attn_fp8pv(const AttnParams& p, int H, int variant, hipStream_t s) {
-  if (variant < 0 || variant >= kNumBf16Variants) return hipErrorInvalidValue;
-  const dim3 grid(p.n_items, H);
   switch (variant) {
-    case 1: hipLaunchKernelGGL((attn_fp8pv_kernel<2, 4, 2>), grid, dim3(256), 0, s, p); break;
-    case 2: hipLaunchKernelGGL((attn_fp8pv_kernel<1, 8, 2>), grid, dim3(512), 0, s, p); break;
-    default: hipLaunchKernelGGL((attn_fp8pv_kernel<1, 4, 2>), grid, dim3(256), 0, s, p); break;
+    case 0: return launch_attn_kernel(attn_fp8pv_kernel<1, 4, 2>, p, H, 256, s);
+    case 1: return launch_attn_kernel(attn_fp8pv_kernel<2, 4, 2>, p, H, 256, s);
+    case 2: return launch_attn_kernel(attn_fp8pv_kernel<1, 8, 2>, p, H, 512, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_attn_f32(const AttnParams& p, int H, hipStream_t s) {
-  hipLaunchKernelGGL(attn_f32_kernel, dim3(p.n_items, H), dim3(256), 0, s, p);
-  return hipGetLastError();
+  if (p.queue) return hipErrorInvalidValue;  // grid mode only
+  return launch(attn_f32_kernel, dim3(p.n_items, H), dim3(256), 0, s, p);
 }
 
 hipError_t launch_attn_fp8(const AttnParams& p, int H, int variant, hipStream_t s) {
-  if (variant < 0 || variant >= kNumFp8Variants) return hipErrorInvalidValue;
-  const dim3 grid(p.n_items, H);
   switch (variant) {
-    case 1: hipLaunchKernelGGL((attn_fp8_kernel<2, 4, 2>), grid, dim3(256), 0, s, p); break;
-    case 2: hipLaunchKernelGGL((attn_fp8_kernel<1, 8, 2>), grid, dim3(512), 0, s, p); break;
-    case 3: hipLaunchKernelGGL((attn_fp8_kernel<2, 8, 2>), grid, dim3(512), 0, s, p); break;
-    default: hipLaunchKernelGGL((attn_fp8_kernel<1, 4, 2>), grid, dim3(256), 0, s, p); break;
+    case 0: return launch_attn_kernel(attn_fp8_kernel<1, 4, 2>, p, H, 256, s);
+    case 1: return launch_attn_kernel(attn_fp8_kernel<2, 4, 2>, p, H, 256, s);
+    case 2: return launch_attn_kernel(attn_fp8_kernel<1, 8, 2>, p, H, 512, s);
+    case 3: return launch_attn_kernel(attn_fp8_kernel<2, 8, 2>, p, H, 512, s);
+    default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_v_transpose_bf16(const bf16* v, int64_t v_ts, int64_t v_hs, bf16* vt, int64_t vt_hs, int64_t vt_ds,
                                    const SeqTable& seqs, int n_tiles, int H, hipStream_t s) {
-  hipLaunchKernelGGL(v_transpose_bf16_kernel, dim3(n_tiles, H), dim3(256), 0, s, v, v_ts, v_hs, vt, vt_hs, vt_ds,
-                     seqs);
-  return hipGetLastError();
+  return launch(v_transpose_bf16_kernel, dim3(n_tiles, H), dim3(256), 0, s, v, v_ts, v_hs, vt, vt_hs, vt_ds, seqs);
 }
 
 hipError_t launch_quant_fp8(const bf16* x, int64_t x_ts, int64_t x_hs, float pre, uint8_t* codes, int64_t c_hs,
                             int64_t c_ds, bool transposed, int64_t out_row0, float* scales, int64_t sc_hs,
                             const SeqTable& seqs, int n_blocks, int H, hipStream_t s) {
-  hipLaunchKernelGGL(quant_fp8_kernel, dim3(n_blocks, H), dim3(256), 0, s, x, x_ts, x_hs, pre, codes, c_hs, c_ds,
-                     transposed ? 1 : 0, out_row0, scales, sc_hs, seqs);
-  return hipGetLastError();
+  return launch(quant_fp8_kernel, dim3(n_blocks, H), dim3(256), 0, s, x, x_ts, x_hs, pre, codes, c_hs, c_ds,
+                transposed ? 1 : 0, out_row0, scales, sc_hs, seqs);
 }
 
 hipError_t launch_scale_max(const float* sk, const float* sv, int64_t sc_hs, int n_blocks, float* vmax, int* kinfo,
                             int H, hipStream_t s) {
-  hipLaunchKernelGGL(scale_max_kernel, dim3(H), dim3(64), 0, s, sk, sv, sc_hs, n_blocks, vmax, kinfo);
-  return hipGetLastError();
+  return launch(scale_max_kernel, dim3(H), dim3(64), 0, s, sk, sv, sc_hs, n_blocks, vmax, kinfo);
 }
 
 }  // namespace vggtx

@@ -50,15 +50,13 @@ static hipError_t ln_dispatch(const float* x, int64_t ldx, const void* g, const 
   switch (C / 64) {
 #define VGGTX_LN_CASE(n)                                                                         \
   case n:                                                                                        \
-    hipLaunchKernelGGL((layernorm_kernel<n, T>), grid, block, 0, s, x, ldx, gg, bb, eps, hh, ldh, rows); \
-    break;
+    return launch(layernorm_kernel<n, T>, grid, block, 0, s, x, ldx, gg, bb, eps, hh, ldh, rows);
     VGGTX_LN_CASE(2) VGGTX_LN_CASE(4) VGGTX_LN_CASE(6) VGGTX_LN_CASE(8) VGGTX_LN_CASE(10) VGGTX_LN_CASE(12)
     VGGTX_LN_CASE(14) VGGTX_LN_CASE(16) VGGTX_LN_CASE(18) VGGTX_LN_CASE(20) VGGTX_LN_CASE(22) VGGTX_LN_CASE(24)
     VGGTX_LN_CASE(26) VGGTX_LN_CASE(28) VGGTX_LN_CASE(30) VGGTX_LN_CASE(32)
 #undef VGGTX_LN_CASE
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_layernorm(const float* x, int64_t ldx, const void* g, const void* b, float eps, void* h, int64_t ldh,
@@ -95,8 +93,7 @@ __global__ __launch_bounds__(256) void row_stats_kernel(const float* x, int64_t 
 hipError_t launch_row_stats(const float* x, int64_t ldx, int rows, int C, float* stats, hipStream_t s) {
   if (rows <= 0) return hipSuccess;
   if (C % 128) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(row_stats_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, x, ldx, rows, C, stats);
-  return hipGetLastError();
+  return launch(row_stats_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, x, ldx, rows, C, stats);
 }
 
 // Seeded synthetic bfloat16 values for the autotuner: a counter-based hash
@@ -116,13 +113,23 @@ __global__ void fill_hash_bf16_kernel(bf16* x, int64_t n, uint64_t seed, float s
 hipError_t launch_fill_hash_bf16(bf16* x, int64_t n, uint64_t seed, float scale, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(fill_hash_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, seed, scale);
-  return hipGetLastError();
+  return launch(fill_hash_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, seed, scale);
+}
+
+// Plain copy (a kernel rather than a runtime copy so that it can be recorded
+// into a graph like every other step of the forward).
+__global__ __launch_bounds__(256) void copy_f32_kernel(const float* src, float* dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t n4 = ((uintptr_t)src % 16 == 0 && (uintptr_t)dst % 16 == 0) ? n / 4 : 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n4; i += stride)
+    ((f32x4*)dst)[i] = ((const f32x4*)src)[i];
+  for (int64_t i = 4 * n4 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s) {
   if (src == dst || n == 0) return hipSuccess;
-  return hipMemcpyAsync(dst, src, n * sizeof(float), hipMemcpyDeviceToDevice, s);
+  const int64_t blocks = std::min<int64_t>((n / 4 + 255) / 256 + 1, 8192);
+  return launch(copy_f32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
 }
 
 }  // namespace vggtx

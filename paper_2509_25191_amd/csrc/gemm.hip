@@ -305,29 +305,27 @@ hipError_t launch_gemm_bf16(const GemmParams& p, Epi epi, hipStream_t s) {
   if (ln && (epi != EPI_QKV && epi != EPI_GELU)) return hipErrorInvalidValue;
   switch (epi) {
     case EPI_QKV:
-      if (ln) hipLaunchKernelGGL((gemm_bf16_kernel<EPI_QKV, true>), grid, block, 0, s, p);
-      else hipLaunchKernelGGL((gemm_bf16_kernel<EPI_QKV, false>), grid, block, 0, s, p);
-      break;
-    case EPI_RESID: hipLaunchKernelGGL((gemm_bf16_kernel<EPI_RESID, false>), grid, block, 0, s, p); break;
+      return ln ? launch(gemm_bf16_kernel<EPI_QKV, true>, grid, block, 0, s, p)
+                : launch(gemm_bf16_kernel<EPI_QKV, false>, grid, block, 0, s, p);
+    case EPI_RESID: return launch(gemm_bf16_kernel<EPI_RESID, false>, grid, block, 0, s, p);
     case EPI_GELU:
-      if (ln) hipLaunchKernelGGL((gemm_bf16_kernel<EPI_GELU, true>), grid, block, 0, s, p);
-      else hipLaunchKernelGGL((gemm_bf16_kernel<EPI_GELU, false>), grid, block, 0, s, p);
-      break;
-    case EPI_EMBED: hipLaunchKernelGGL((gemm_bf16_kernel<EPI_EMBED, false>), grid, block, 0, s, p); break;
+      return ln ? launch(gemm_bf16_kernel<EPI_GELU, true>, grid, block, 0, s, p)
+                : launch(gemm_bf16_kernel<EPI_GELU, false>, grid, block, 0, s, p);
+    case EPI_EMBED: return launch(gemm_bf16_kernel<EPI_EMBED, false>, grid, block, 0, s, p);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_gemm_f32(const GemmParams& p, Epi epi, hipStream_t s) {
   if (p.ln_g || p.stats) return hipErrorInvalidValue;  // the float32 path runs its LayerNorms separately
   dim3 grid(p.N / 64, (p.M + 63) / 64), block(256);
   switch (epi) {
-    case EPI_QKV: hipLaunchKernelGGL(gemm_f32_kernel<EPI_QKV>, grid, block, 0, s, p); break;
-    case EPI_RESID: hipLaunchKernelGGL(gemm_f32_kernel<EPI_RESID>, grid, block, 0, s, p); break;
-    case EPI_GELU: hipLaunchKernelGGL(gemm_f32_kernel<EPI_GELU>, grid, block, 0, s, p); break;
-    case EPI_EMBED: hipLaunchKernelGGL(gemm_f32_kernel<EPI_EMBED>, grid, block, 0, s, p); break;
+    case EPI_QKV: return launch(gemm_f32_kernel<EPI_QKV>, grid, block, 0, s, p);
+    case EPI_RESID: return launch(gemm_f32_kernel<EPI_RESID>, grid, block, 0, s, p);
+    case EPI_GELU: return launch(gemm_f32_kernel<EPI_GELU>, grid, block, 0, s, p);
+    case EPI_EMBED: return launch(gemm_f32_kernel<EPI_EMBED>, grid, block, 0, s, p);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 }  // namespace vggtx

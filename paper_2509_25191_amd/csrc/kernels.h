@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "common.h"
+#include "launch.h"
 
 namespace vggtx {
 
@@ -36,6 +37,13 @@ struct AttnParams {
   const int* kinfo;                      // FP8: per (head, key block) E8M0 codes, 2 ints each (launch_scale_max)
   float scale_log2;                      // log2(e) / sqrt(D)
   int n_items;                           // query tiles per head
+  // Queue mode (BF16, FP8 P V and FP8 kernels): queue != null points at a
+  // work counter in device memory; the launcher zeroes it, and each of the
+  // n_heads * n_items workgroups takes its work item from it when it starts
+  // (longest sequence first, see take_work).  Null: workgroup (x, y) runs
+  // item x of head y.
+  int* queue;
+  int n_heads;
   SeqTable seqs;
 };
 

@@ -46,6 +46,17 @@ struct KernelTimer {
   int64_t dropped = 0;
 };
 
+// A forward recorded once and replayed as a HIP graph: the launches of the
+// last binding (kernel, shape, argument bytes) and the instantiated graph,
+// one kernel node per launch in a chain.
+struct GraphEntry {
+  std::vector<vggtx::LaunchRecord> launches;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipGraphNode_t> nodes;
+  uint64_t last_use = 0;
+};
+
 struct vggtx_ctx {
   int device;
   char arch[64];
@@ -54,6 +65,10 @@ struct vggtx_ctx {
   int bf16_variant;  // BF16 attention kernel variant (index into the BF16 variant table)
   int fp8_variant;   // FP8 attention kernel variant (index into the FP8 variant table)
   bool timing_off;   // set while an entry point that must not create events runs
+  bool graph_mode = false;          // vggtx_graph_mode
+  std::vector<GraphEntry> graphs;   // at most kMaxGraphs, least recently used evicted
+  uint64_t graph_clock = 0;
+  int64_t graph_stats[4] = {0, 0, 0, 0};  // cached graphs, builds, node updates, launches
 };
 
 // Device scratch of the entry point that allocates nothing
@@ -267,6 +282,7 @@ struct Ws {
   float* sv = nullptr;
   float* vmax = nullptr;     // [H]
   int* kinfo = nullptr;      // [H, nblk, 2] E8M0 codes
+  int* queue = nullptr;      // BF16 / FP8: work counter of queue-mode attention launches
   size_t total = 0;
 };
 
@@ -315,6 +331,7 @@ Ws carve(const vggtx_config& c, const WsShape& sh, vggtx_prec prec, char* base) 
     w.vmax = (float*)take(H * 4);
     w.kinfo = (int*)take(H * sh.nblk * 8);
   }
+  if (prec != VGGTX_F32) w.queue = (int*)take(4);
   w.total = off;
   return w;
 }
@@ -331,6 +348,7 @@ vggtx_status check_cfg(const vggtx_config* c) {
   if (!(c->ln_eps > 0.f)) return fail(VGGTX_E_INVALID, "ln_eps must be positive");
   if (c->frame_chunk <= 0) return fail(VGGTX_E_INVALID, "frame_chunk must be positive");
   if (c->tokens_inplace != 0 && c->tokens_inplace != 1) return fail(VGGTX_E_INVALID, "tokens_inplace must be 0 or 1");
+  if (c->attn_schedule != 0 && c->attn_schedule != 1) return fail(VGGTX_E_INVALID, "attn_schedule must be 0 or 1");
   return VGGTX_OK;
 }
 
@@ -479,6 +497,7 @@ struct AttnIO {
   uint8_t *q8, *k8, *v8t;
   float *sq, *sk, *sv, *vmax;
   int* kinfo;
+  int* queue;       // work counter (queue-mode global attention), or null
   int64_t npad;     // columns of vt / v8t
   int64_t nblk;     // per-head stride of the FP8 scale arrays
   int64_t n_tokens; // rows of the q8 / k8 code arrays
@@ -506,6 +525,10 @@ vggtx_status run_attention(vggtx_ctx* ctx, int cls, const AttnIO& io, const Seqs
   p.v = io.v; p.v_ts = io.v_ts; p.v_hs = io.v_hs;
   p.o = io.o; p.o_ts = io.o_ts; p.o_hs = io.o_hs;
   p.scale_log2 = kLog2e / sqrtf((float)kHeadDim);
+  p.n_heads = H;
+  // queue mode for global attention; frame attention's items are short and
+  // uniform, a grid launch serves them as well
+  if (prec != VGGTX_F32 && cls == VGGTX_K_ATTN_GLOBAL && ctx->cfg.attn_schedule == 0) p.queue = io.queue;
   if (prec == VGGTX_F32) {
     for (auto& tn : make_tables(s, attn_block_rows(0, 1))) {
       p.seqs = tn.first; p.n_items = tn.second;
@@ -687,6 +710,7 @@ vggtx_status block_global(const BlockRun& br, const vggtx_block_w& w, const Seqs
   io.vt = br.ws.vt;
   io.q8 = br.ws.q8; io.k8 = br.ws.k8; io.v8t = br.ws.v8t;
   io.sq = br.ws.sq; io.sk = br.ws.sk; io.sv = br.ws.sv; io.vmax = br.ws.vmax; io.kinfo = br.ws.kinfo;
+  io.queue = br.ws.queue;
   io.npad = fp8 || fp8pv ? br.sh.npad : br.sh.vt_cols;
   io.nblk = br.sh.nblk;
   io.n_tokens = N;
@@ -865,6 +889,7 @@ Ws carve_attn(int H, int64_t N, int64_t npad, int64_t nblk, vggtx_prec prec, cha
     w.vmax = (float*)take(H * 4);
     w.kinfo = (int*)take(H * nblk * 8);
   }
+  if (prec != VGGTX_F32) w.queue = (int*)take(4);
   w.total = off;
   return w;
 }
@@ -901,6 +926,7 @@ vggtx_status attn_entry(vggtx_handle h, int cls, const void* q, const void* k, c
   io.vt = w.vt;
   io.q8 = w.q8; io.k8 = w.k8; io.v8t = w.v8t;
   io.sq = w.sq; io.sk = w.sk; io.sv = w.sv; io.vmax = w.vmax; io.kinfo = w.kinfo;
+  io.queue = w.queue;
   io.npad = npad; io.nblk = nblk; io.n_tokens = N;
   return run_attention(h, cls, io, s, H, prec, (hipStream_t)stream);
 }
@@ -1172,6 +1198,145 @@ vggtx_status ga_impl(vggtx_handle h, const vggtx_ga_config* cfg, int n_cams, con
 }  // namespace
 
 // ====================================================================== C-ABI
+namespace vggtx {
+Recording*& active_recording() {
+  thread_local Recording* r = nullptr;
+  return r;
+}
+}  // namespace vggtx
+
+namespace {
+
+constexpr size_t kMaxGraphs = 8;
+
+void graph_free(GraphEntry& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
+// Same kernels with the same launch shapes and argument sizes, in order: a
+// graph built for `a` can run `b` once its node arguments are updated.
+bool same_structure(const std::vector<LaunchRecord>& a, const std::vector<LaunchRecord>& b) {
+  if (a.size() != b.size()) return false;
+  for (size_t i = 0; i < a.size(); ++i) {
+    const LaunchRecord &x = a[i], &y = b[i];
+    if (x.func != y.func || x.shm != y.shm || x.args.size() != y.args.size() || x.offs != y.offs ||
+        x.grid.x != y.grid.x || x.grid.y != y.grid.y || x.grid.z != y.grid.z || x.block.x != y.block.x ||
+        x.block.y != y.block.y || x.block.z != y.block.z)
+      return false;
+  }
+  return true;
+}
+
+hipKernelNodeParams node_params(LaunchRecord& r, std::vector<void*>& argv) {
+  argv.resize(r.offs.size());
+  for (size_t i = 0; i < r.offs.size(); ++i) argv[i] = r.args.data() + r.offs[i];
+  hipKernelNodeParams kp;
+  memset(&kp, 0, sizeof(kp));
+  kp.func = const_cast<void*>(r.func);
+  kp.gridDim = r.grid;
+  kp.blockDim = r.block;
+  kp.sharedMemBytes = r.shm;
+  kp.kernelParams = argv.data();
+  kp.extra = nullptr;
+  return kp;
+}
+
+// Runs a recorded forward on `st` through the handle's graph cache: a graph
+// with the same structure gets the arguments of the launches that changed
+// (hipGraphExecKernelNodeSetParams, so reallocated buffers are followed
+// without a rebuild); otherwise a new graph is built and instantiated.
+vggtx_status graph_run(vggtx_ctx* h, Recording& rec, hipStream_t st) {
+  GraphEntry* hit = nullptr;
+  for (auto& g : h->graphs)
+    if (same_structure(g.launches, rec.launches)) {
+      hit = &g;
+      break;
+    }
+  std::vector<void*> argv;
+  if (hit) {
+    for (size_t i = 0; i < rec.launches.size(); ++i) {
+      LaunchRecord& r = rec.launches[i];
+      if (r.args == hit->launches[i].args) continue;
+      const hipKernelNodeParams kp = node_params(r, argv);
+      VGGTX_HIP(hipGraphExecKernelNodeSetParams(hit->exec, hit->nodes[i], &kp));
+      hit->launches[i].args = r.args;
+      ++h->graph_stats[2];
+    }
+  } else {
+    if (h->graphs.size() >= kMaxGraphs) {
+      auto lru = std::min_element(h->graphs.begin(), h->graphs.end(),
+                                  [](const GraphEntry& a, const GraphEntry& b) { return a.last_use < b.last_use; });
+      graph_free(*lru);
+      h->graphs.erase(lru);
+    }
+    GraphEntry g;
+    VGGTX_HIP(hipGraphCreate(&g.graph, 0));
+    hipGraphNode_t prev = nullptr;
+    for (auto& r : rec.launches) {
+      const hipKernelNodeParams kp = node_params(r, argv);
+      hipGraphNode_t node;
+      const hipError_t e = hipGraphAddKernelNode(&node, g.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+      if (e != hipSuccess) {
+        graph_free(g);
+        return fail(VGGTX_E_HIP, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+      }
+      g.nodes.push_back(node);
+      prev = node;
+    }
+    const hipError_t e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      graph_free(g);
+      return fail(VGGTX_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    g.launches = std::move(rec.launches);
+    h->graphs.push_back(std::move(g));
+    hit = &h->graphs.back();
+    ++h->graph_stats[1];
+  }
+  hit->last_use = ++h->graph_clock;
+  h->graph_stats[0] = (int64_t)h->graphs.size();
+  VGGTX_HIP(hipGraphLaunch(hit->exec, st));
+  ++h->graph_stats[3];
+  return VGGTX_OK;
+}
+
+// The aggregate entry points: direct, or (graph mode) recorded and run as a
+// graph.  Validation errors return before anything is recorded or enqueued.
+vggtx_status aggregate_entry(vggtx_handle h, const float* tokens, const int32_t* frame_offsets, int n_scenes, int P,
+                             const vggtx_pair_w* w, int depth, const int32_t* out_layers, int n_out, void* out,
+                             vggtx_dtype out_dtype, vggtx_prec prec, void* ws, size_t ws_bytes, void* stream) {
+  if (!h || !h->graph_mode)
+    return aggregate_impl(h, tokens, frame_offsets, n_scenes, P, w, depth, out_layers, n_out, out, out_dtype, prec,
+                          ws, ws_bytes, stream);
+  Recording rec;
+  struct Scope {  // recording on, timing events off, for the host pass
+    vggtx_ctx* h;
+    bool saved;
+    Scope(vggtx_ctx* c, Recording* r) : h(c), saved(c->timing_off) {
+      active_recording() = r;
+      h->timing_off = true;
+    }
+    ~Scope() {
+      active_recording() = nullptr;
+      h->timing_off = saved;
+    }
+  };
+  {
+    Scope sc(h, &rec);
+    VGGTX_TRY(aggregate_impl(h, tokens, frame_offsets, n_scenes, P, w, depth, out_layers, n_out, out, out_dtype, prec,
+                             ws, ws_bytes, stream));
+  }
+  if (rec.launches.empty()) return VGGTX_OK;
+  DeviceGuard dg(h->device);
+  if (!dg.ok) return fail(VGGTX_E_HIP, "cannot select device %d", h->device);
+  return graph_run(h, rec, (hipStream_t)stream);
+}
+
+}  // namespace
+
 extern "C" {
 
 vggtx_status vggtx_create(vggtx_handle* h, int device, const vggtx_config* cfg) {
@@ -1215,6 +1380,10 @@ vggtx_status vggtx_create(vggtx_handle* h, int device, const vggtx_config* cfg) 
 
 vggtx_status vggtx_destroy(vggtx_handle h) {
   if (!h) return VGGTX_OK;
+  {
+    DeviceGuard dg(h->device);
+    for (auto& g : h->graphs) graph_free(g);
+  }
   for (int i = 0; i < 2 * h->timer.created; ++i) (void)hipEventDestroy(h->timer.ev[i]);
   delete h;
   return VGGTX_OK;
@@ -1233,15 +1402,34 @@ vggtx_status vggtx_aggregate(vggtx_handle h, const float* tokens, int S, int P, 
                              void* ws, size_t ws_bytes, void* stream) {
   if (S < 0) return fail(VGGTX_E_INVALID, "S = %d", S);
   const int32_t off[2] = {0, S};
-  return aggregate_impl(h, tokens, off, 1, P, w, depth, out_layers, n_out, out, out_dtype, prec, ws, ws_bytes, stream);
+  return aggregate_entry(h, tokens, off, 1, P, w, depth, out_layers, n_out, out, out_dtype, prec, ws, ws_bytes, stream);
 }
 
 vggtx_status vggtx_aggregate_varlen(vggtx_handle h, const float* tokens, const int32_t* frame_offsets, int n_scenes,
                                     int P, const vggtx_pair_w* w, int depth, const int32_t* out_layers, int n_out,
                                     void* out, vggtx_dtype out_dtype, vggtx_prec prec, void* ws, size_t ws_bytes,
                                     void* stream) {
-  return aggregate_impl(h, tokens, frame_offsets, n_scenes, P, w, depth, out_layers, n_out, out, out_dtype, prec, ws,
-                        ws_bytes, stream);
+  return aggregate_entry(h, tokens, frame_offsets, n_scenes, P, w, depth, out_layers, n_out, out, out_dtype, prec, ws,
+                         ws_bytes, stream);
+}
+
+vggtx_status vggtx_graph_mode(vggtx_handle h, int enable) {
+  if (!h) return fail(VGGTX_E_INVALID, "handle is null");
+  if (enable != 0 && enable != 1) return fail(VGGTX_E_INVALID, "enable must be 0 or 1");
+  h->graph_mode = enable != 0;
+  if (!enable) {
+    DeviceGuard dg(h->device);
+    for (auto& g : h->graphs) graph_free(g);
+    h->graphs.clear();
+    h->graph_stats[0] = 0;
+  }
+  return VGGTX_OK;
+}
+
+vggtx_status vggtx_graph_stats(vggtx_handle h, int64_t* stats) {
+  if (!h || !stats) return fail(VGGTX_E_INVALID, "handle / stats is null");
+  for (int i = 0; i < 4; ++i) stats[i] = h->graph_stats[i];
+  return VGGTX_OK;
 }
 
 vggtx_status vggtx_block(vggtx_handle h, const float* x_in, float* x_out, const int32_t* seq_offsets, int n_seq,

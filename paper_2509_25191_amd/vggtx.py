@@ -19,7 +19,7 @@ __all__ = [
     "quantize_fp8", "status_str", "last_error", "BLOCK_FIELDS", "timing_enable", "timing_read", "timing_poll",
     "autotune_workspace_size", "autotune", "EmbedW", "EMBED_FIELDS", "embed_workspace_size", "embed",
     "GaConfig", "ga_config_default", "ga_select_pairs", "ga_workspace_size", "ga_align", "auc30",
-    "pack_head_inputs",
+    "pack_head_inputs", "SCHEDULE_QUEUE", "SCHEDULE_GRID", "graph_mode", "graph_stats",
     "K_ATTN_GLOBAL", "K_ATTN_FRAME", "K_GEMM", "K_OTHER",
 ]
 
@@ -46,7 +46,10 @@ class VggtxError(RuntimeError):
 class Config(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("heads", ctypes.c_int), ("head_dim", ctypes.c_int),
                 ("mlp_hidden", ctypes.c_int), ("ln_eps", ctypes.c_float), ("frame_chunk", ctypes.c_int),
-                ("tokens_inplace", ctypes.c_int)]
+                ("tokens_inplace", ctypes.c_int), ("attn_schedule", ctypes.c_int)]
+
+# Config.attn_schedule
+SCHEDULE_QUEUE, SCHEDULE_GRID = 0, 1
 
 
 class BlockW(ctypes.Structure):
@@ -116,6 +119,8 @@ def load():
                            ctypes.POINTER(ctypes.c_int64), vp, vp, vp, vp, vp, vp, vp, sz, vp],
         "vggtx_auc30": [vp, vp, vp, vp, vp, i32, i32, vp, vp, vp],
         "vggtx_pack_head_inputs": [vp, vp, i32, i32, i32, i32, i32, i32, vp, vp],
+        "vggtx_graph_mode": [vp, i32],
+        "vggtx_graph_stats": [vp, ctypes.POINTER(ctypes.c_int64)],
         "vggtx_timing_enable": [vp, i32],
         "vggtx_timing_read": [vp, ctypes.POINTER(Timing), ctypes.POINTER(ctypes.c_int64)],
         "vggtx_timing_poll": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -163,9 +168,10 @@ def _i32_array(vals: Sequence[int]):
 
 
 def create(device: int, dim: int, heads: int, head_dim: int = 64, mlp_hidden: Optional[int] = None,
-           ln_eps: float = 1e-6, frame_chunk: int = 128, tokens_inplace: bool = False) -> ctypes.c_void_p:
+           ln_eps: float = 1e-6, frame_chunk: int = 128, tokens_inplace: bool = False,
+           attn_schedule: int = SCHEDULE_QUEUE) -> ctypes.c_void_p:
     cfg = Config(dim, heads, head_dim, mlp_hidden if mlp_hidden is not None else 4 * dim, ln_eps, frame_chunk,
-                 1 if tokens_inplace else 0)
+                 1 if tokens_inplace else 0, int(attn_schedule))
     h = ctypes.c_void_p()
     _check(load().vggtx_create(ctypes.byref(h), int(device), ctypes.byref(cfg)))
     return h
@@ -410,6 +416,17 @@ def pack_head_inputs(h, feats: torch.Tensor, grid_h: int, grid_w: int, out: Opti
     return out
 
 
+def graph_mode(h, enable: bool = True) -> None:
+    _check(load().vggtx_graph_mode(h, 1 if enable else 0))
+
+
+def graph_stats(h) -> dict:
+    """{"graphs", "builds", "node_updates", "launches"} of the handle's graph cache."""
+    arr = (ctypes.c_int64 * 4)()
+    _check(load().vggtx_graph_stats(h, arr))
+    return dict(zip(("graphs", "builds", "node_updates", "launches"), list(arr)))
+
+
 def timing_enable(h, enable: bool = True) -> None:
     _check(load().vggtx_timing_enable(h, 1 if enable else 0))
 
@@ -437,8 +454,8 @@ class Handle:
 
     def __init__(self, device: int = 0, dim: int = 1024, heads: int = 16, head_dim: int = 64,
                  mlp_hidden: Optional[int] = None, ln_eps: float = 1e-6, frame_chunk: int = 128,
-                 tokens_inplace: bool = False):
-        self.h = create(device, dim, heads, head_dim, mlp_hidden, ln_eps, frame_chunk, tokens_inplace)
+                 tokens_inplace: bool = False, attn_schedule: int = SCHEDULE_QUEUE):
+        self.h = create(device, dim, heads, head_dim, mlp_hidden, ln_eps, frame_chunk, tokens_inplace, attn_schedule)
 
     def close(self):
         if self.h is not None:

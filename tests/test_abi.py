@@ -60,6 +60,8 @@ def test_create_validates_config_before_device():
     assert lib.vggtx_create(ctypes.byref(h), 0, ctypes.byref(bad_eps)) == 1
     bad_inplace = vg.Config(256, 4, 64, 1024, 1e-6, 128, 2)  # tokens_inplace is a 0/1 flag
     assert lib.vggtx_create(ctypes.byref(h), 0, ctypes.byref(bad_inplace)) == 1
+    bad_sched = vg.Config(256, 4, 64, 1024, 1e-6, 128, 0, 2)  # attn_schedule is 0 (queue) or 1 (grid)
+    assert lib.vggtx_create(ctypes.byref(h), 0, ctypes.byref(bad_sched)) == 1
     assert h.value is None
 
 
