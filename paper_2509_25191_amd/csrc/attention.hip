@@ -146,22 +146,28 @@ __device__ __forceinline__ int pack_e4m3x4(float e0, float e1, float e2, float e
 //             product in key order.
 //   Vs[d][.]  V^T tile in key order.
 //
-// Softmax with a lazy shift.  Full key tiles after the first take the
-// probabilities against the current shift m (the largest logit seen when m
-// last moved), p = 2^(c2 s - c2 m), with no maximum search: softmax is
-// shift-invariant, so m only has to keep p finite.  While the tile's row sum
-// stays below 2^32 every p of the row is below it, and O and l (float32)
-// stay far from overflow.  A row sum at or above 2^32 (an infinity or a NaN
-// included; tested on the bits) sends the query block to the exact step: its
-// scores are recomputed from the K tile still in LDS, m moves to the row
-// maximum, O and l are rescaled by 2^(c2 m_old - c2 m_new), and the
-// probabilities are taken again.  The first and the partial last tile always
-// take the exact step.  The row sum runs on the matrix core: a 16x16x32 MFMA
-// with a lane-selector A operand over the bfloat16 probability registers of
-// the P V product (read as its B operand, they are 16 columns whose four
-// k-groups hold queries n, n+16, n, n+16; selector rows 4j..4j+3 take the
-// k-groups of parity j&1, so output lane l receives the sum for its own query
-// l%32), so l is summed from the same rounded probabilities as O.
+// Softmax with a lazy shift, applied inside the score MFMA.  Q is taken
+// times c2 = log2(e)/sqrt(D) (rounded to bfloat16 once, when its fragments
+// are loaded), so the MFMA gives logits in base 2, and each query's shift m
+// enters the product as a fifth k-step: A = 1 in k-slot 0 of every key row,
+// B = -m (bfloat16) in k-slot 0 of the query's column, so the accumulator
+// starts at -m and the probabilities are p = 2^s with no per-score
+// arithmetic before the exponential.  Full key tiles after the first take
+// p against the current m (the row maximum, rounded to bfloat16, when m last
+// moved) with no maximum search: softmax is shift-invariant, so m only has
+// to keep p finite.  While the tile's row sum stays below 2^32 every p of the
+// row is below it, and O and l (float32) stay far from overflow.  A row sum
+// at or above 2^32 (an infinity or a NaN included; tested on the bits) sends
+// the query block to the exact step: its scores are recomputed from the K
+// tile still in LDS, m moves up to the row maximum (rounded), O and l are
+// rescaled by 2^(m_old - m_new), and the probabilities are taken again.  The
+// first and the partial last tile always take the exact step.  The row sum
+// runs on the matrix core: a 16x16x32 MFMA with a lane-selector A operand
+// over the bfloat16 probability registers of the P V product (read as its B
+// operand, they are 16 columns whose four k-groups hold queries n, n+16, n,
+// n+16; selector rows 4j..4j+3 take the k-groups of parity j&1, so output
+// lane l receives the sum for its own query l%32), so l is summed from the
+// same rounded probabilities as O.
 //
 // Issue order: the score MFMAs of query block qb+1 and the P V MFMAs of block
 // qb-1 are issued between the exponentials of block qb.
@@ -186,14 +192,22 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_bf16_kernel(AttnParams p) {
   const bf16x8 zero8 = {};
   const bf16 sv = (((lane >> 2) ^ (lane >> 4)) & 1) ? (bf16)0.0f : (bf16)1.0f;  // row-sum selector
   const bf16x8 sel8 = {sv, sv, sv, sv, sv, sv, sv, sv};
+  const float c2 = p.scale_log2;
   bf16x8 qf[QB][4];
+  bf16x8 negm[QB];  // B operand of the shift step: -m in k-slot 0 of lane group 0
 #pragma unroll
   for (int qb = 0; qb < QB; ++qb) {
     const int row = it.q0 + (wave * QB + qb) * 32 + r32;
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 4; ++c) {
       qf[qb][c] = row < it.s1 ? *(const bf16x8*)(Q + row * p.q_ts + 16 * c + 8 * g) : zero8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) qf[qb][c][j] = f2bf(bf2f(qf[qb][c][j]) * c2);
+    }
+    negm[qb] = zero8;
   }
+  bf16x8 ones8 = zero8;  // A operand of the shift step: 1 in k-slot 0 of every key row
+  if (g == 0) ones8[0] = (bf16)1.0f;
 
   // Tile t into LDS buffer buf: wave w moves the 8-row blocks w, w + NW, ...
   // of both tiles; lane l fills row 8 * block + l / 8, granule slot l % 8.
@@ -219,10 +233,9 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_bf16_kernel(AttnParams p) {
   for (int qb = 0; qb < QB; ++qb) {
     oacc[qb][0] = f32x16{};
     oacc[qb][1] = f32x16{};
-    m_run[qb] = -INFINITY;
+    m_run[qb] = 0.f;  // the shift held in negm (set by the first tile)
     l_run[qb] = 0.f;
   }
-  const float c2 = p.scale_log2;
   const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
 
   dma(0, 0);
@@ -251,7 +264,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_bf16_kernel(AttnParams p) {
     auto score = [&](int qb) {
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb) {
-        s[qb][kb] = f32x16{};
+        s[qb][kb] = mfma_bf16(ones8, negm[qb], f32x16{});
 #pragma unroll
         for (int c = 0; c < 4; ++c) s[qb][kb] = mfma_bf16(kf[kb][c], qf[qb][c], s[qb][kb]);
       }
@@ -265,12 +278,11 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_bf16_kernel(AttnParams p) {
           for (int h = 0; h < 2; ++h) oacc[qb][db] = mfma_bf16(vf[db][kb][h], pb[qb][kb][h], oacc[qb][db]);
     };
     auto probs = [&](int qb, const f32x16& a, const f32x16& b) {
-      const float mc = m_run[qb] * c2;
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb) {
         const f32x16& x = kb ? b : a;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) pb[qb][kb][i >> 3][i & 7] = f2bf(fast_exp2(__builtin_fmaf(x[i], c2, -mc)));
+        for (int i = 0; i < 16; ++i) pb[qb][kb][i >> 3][i & 7] = f2bf(fast_exp2(x[i]));
       }
     };
     auto rowsum = [&](int qb) {
@@ -281,8 +293,10 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_bf16_kernel(AttnParams p) {
         for (int h = 0; h < 2; ++h) r = __builtin_amdgcn_mfma_f32_16x16x32_bf16(sel8, pb[qb][kb][h], r, 0, 0, 0);
       return r[0];
     };
-    // exact step: mask, row maximum, move m (rescaling O and l), probabilities
+    // exact step: mask, row maximum, move m (rescaling O and l), probabilities.
+    // The scores a, b are relative to the current m.
     auto exact = [&](int qb, f32x16& a, f32x16& b, auto is_first) {
+      constexpr bool FIRST_ = decltype(is_first)::value;
       if (MASKED) {
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
@@ -291,19 +305,26 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_bf16_kernel(AttnParams p) {
             if (kt + kb * 32 + 16 * (i >> 3) + 8 * g + (i & 7) >= it.s1) (kb ? b : a)[i] = -INFINITY;
       }
       const float mx = lane_swap_max(max32(a, b));
-      if (decltype(is_first)::value) {
-        m_run[qb] = mx;  // O and l are still zero
-      } else {
-        const float m_new = __builtin_fmaxf(m_run[qb], mx);
-        const float alpha = fast_exp2((m_run[qb] - m_new) * c2);
+      // the new m, rounded to bfloat16 (the shift enters the MFMA in that type);
+      // on the first tile m starts at 0 and O and l are still zero
+      const float base = FIRST_ ? 0.f : m_run[qb];
+      const float d = bf2f(f2bf(base + (FIRST_ ? mx : __builtin_fmaxf(mx, 0.f)))) - base;
+      if (!FIRST_) {
+        const float alpha = fast_exp2(-d);
         l_run[qb] *= alpha;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           oacc[qb][0][i] *= alpha;
           oacc[qb][1][i] *= alpha;
         }
-        m_run[qb] = m_new;
       }
+      m_run[qb] = base + d;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        a[i] -= d;
+        b[i] -= d;
+      }
+      if (g == 0) negm[qb][0] = f2bf(-m_run[qb]);
       probs(qb, a, b);
     };
 
@@ -340,7 +361,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_bf16_kernel(AttnParams p) {
         f32x16 r[2];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
-          r[kb] = f32x16{};
+          r[kb] = mfma_bf16(ones8, negm[qb], f32x16{});
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const int rr = kb * 32 + r32;
