@@ -20,12 +20,13 @@ def _kv(path):
 
 
 def test_traffic_lookup_only_for_the_profiled_source(tmp_path, monkeypatch):
-    assert bench.measured_traffic("fp8", 200) is None  # counters exist for S=1000 only
-    prof = os.path.join(bench.ROOT, "profiles", "attn_fp8_kernel_vggt_l_s1000_traffic.txt")
+    assert bench.measured_traffic("bf16", 200) is None  # counters exist for S=1000 only
+    assert bench.measured_traffic("fp8", 1000) is None  # and for the BF16 kernel only
+    prof = os.path.join(bench.ROOT, "profiles", "attn_bf16_kernel_vggt_l_s1000_traffic.txt")
     src = os.path.join(bench.ROOT, "paper_2509_25191_amd", "csrc", "attention.hip")
     kv = _kv(prof)
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    got = bench.measured_traffic("fp8", 1000)
+    got = bench.measured_traffic("bf16", 1000)
     if kv["attention_hip_sha256"] == digest:
         assert got == float(kv["hbm_bytes_per_launch"]) and got > 0
         assert abs(got - float(kv["fetch_bytes_per_launch"]) - float(kv["write_bytes_per_launch"])) <= 1e-6 * got
@@ -37,7 +38,7 @@ def test_traffic_lookup_only_for_the_profiled_source(tmp_path, monkeypatch):
     shutil.copy(prof, tmp_path / "profiles")
     (tmp_path / "paper_2509_25191_amd" / "csrc" / "attention.hip").write_bytes(open(src, "rb").read() + b"\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("fp8", 1000) is None
+    assert bench.measured_traffic("bf16", 1000) is None
 
 
 def test_more_than_one_gpu_is_refused():
