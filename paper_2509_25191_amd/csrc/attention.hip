@@ -430,9 +430,11 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_bf16_kernel(AttnParams p) {
 // MFMA, and the V^T tile (64 d rows of 64 one-byte keys, 16-byte granules
 // swizzled with lds_swz4) is read in key order.
 //
-// Probabilities: p = 2^(c2 s - c2 m + log2(448) - 2), i.e. the row maximum is
-// placed two binades below 448 when m moves; later full tiles skip the
-// maximum search and convert against the current m.  A score that rose more
+// Probabilities: the score MFMA works on Q times c2 = log2(e)/sqrt(D) and
+// subtracts the shift sh in an extra k-step (as in attn_bf16_kernel), so
+// p = 2^(s - sh) with sh = m - (log2(448) - 2), i.e. the row maximum m is
+// placed two binades below 448 when it moves (sh rounded to bfloat16); later
+// full tiles skip the maximum search and convert against the current sh.  A score that rose more
 // than about two binades above the placed maximum converts to the E4M3 NaN
 // code (the hardware conversion returns NaN above 464); the row-sum MFMA
 // (16x16x128 with the lane selector, over the same E4M3 codes as the P V
@@ -472,6 +474,19 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8pv_kernel(AttnParams p) 
     for (int c = 0; c < 4; ++c)
       qf[qb][c] = row < it.s1 ? *(const bf16x8*)(Q + row * p.q_ts + 16 * c + 8 * g) : zero8;
   }
+  // shift step of the score MFMA (as in attn_bf16_kernel): Q times c2, and
+  // -sh (bfloat16) in k-slot 0 against a ones column, sh = the applied shift
+  bf16x8 negm[QB];
+  bf16x8 ones8 = zero8;
+  if (g == 0) ones8[0] = (bf16)1.0f;
+#pragma unroll
+  for (int qb = 0; qb < QB; ++qb) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) qf[qb][c][j] = f2bf(bf2f(qf[qb][c][j]) * p.scale_log2);
+    negm[qb] = zero8;
+  }
 
   // Tile t into LDS buffer buf.  K: 8 blocks of 8 rows x 128 bytes; V^T: 4
   // blocks of 16 rows x 64 bytes; wave w moves K blocks w, w + NW, ... and V
@@ -506,10 +521,9 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8pv_kernel(AttnParams p) 
   for (int qb = 0; qb < QB; ++qb) {
     oacc[qb][0] = f32x16{};
     oacc[qb][1] = f32x16{};
-    m_run[qb] = -INFINITY;
+    m_run[qb] = 0.f;  // the applied shift, set by the first tile
     l_run[qb] = 0.f;
   }
-  const float c2 = p.scale_log2;
   const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
 
   dma(0, 0);
@@ -536,7 +550,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8pv_kernel(AttnParams p) 
     auto score = [&](int qb) {
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb) {
-        s[qb][kb] = f32x16{};
+        s[qb][kb] = mfma_bf16(ones8, negm[qb], f32x16{});
 #pragma unroll
         for (int c = 0; c < 4; ++c) s[qb][kb] = mfma_bf16(kf[kb][c], qf[qb][c], s[qb][kb]);
       }
@@ -545,18 +559,16 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8pv_kernel(AttnParams p) 
       oacc[qb][0] = mfma_fp8_scaled(vf[0], pw[qb], oacc[qb][0], ev, 127);
       oacc[qb][1] = mfma_fp8_scaled(vf[1], pw[qb], oacc[qb][1], ev, 127);
     };
-    // E4M3 probabilities of one query block, in key order (32 per lane)
+    // E4M3 probabilities of one query block, in key order (32 per lane); the
+    // scores already hold s - sh
     auto probs = [&](int qb, const f32x16& a, const f32x16& b) {
-      const float mc = m_run[qb] * c2 - kPlace;
 #pragma unroll
       for (int kb = 0; kb < 2; ++kb) {
         const f32x16& x = kb ? b : a;
 #pragma unroll
         for (int i = 0; i < 16; i += 4)
-          pw[qb][(16 * kb + i) >> 2] = pack_e4m3x4(fast_exp2(__builtin_fmaf(x[i], c2, -mc)),
-                                                   fast_exp2(__builtin_fmaf(x[i + 1], c2, -mc)),
-                                                   fast_exp2(__builtin_fmaf(x[i + 2], c2, -mc)),
-                                                   fast_exp2(__builtin_fmaf(x[i + 3], c2, -mc)));
+          pw[qb][(16 * kb + i) >> 2] =
+              pack_e4m3x4(fast_exp2(x[i]), fast_exp2(x[i + 1]), fast_exp2(x[i + 2]), fast_exp2(x[i + 3]));
       }
     };
     auto rowsum = [&](int qb) { return mfma_fp8_16(sel8, pw[qb], f32x4{})[0]; };
@@ -569,19 +581,29 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8pv_kernel(AttnParams p) 
             if (kt + 32 * g + 16 * kb + i >= it.s1) (kb ? b : a)[i] = -INFINITY;
       }
       const float mx = lane_swap_max(max32(a, b));
-      if (decltype(is_first)::value) {
-        m_run[qb] = mx;  // O and l are still zero
-      } else {
-        const float m_new = __builtin_fmaxf(m_run[qb], mx);
-        const float alpha = fast_exp2((m_run[qb] - m_new) * c2);
+      // scores relative to the applied shift sh = m_run; the row maximum is
+      // placed kPlace binades up when it moves (sh rounded to bfloat16, the
+      // type it enters the MFMA in); on the first tile O and l are zero
+      constexpr bool F_ = decltype(is_first)::value;
+      const float base = F_ ? 0.f : m_run[qb];
+      const float want = F_ ? mx - kPlace : __builtin_fmaxf(mx - kPlace, 0.f);
+      const float d = bf2f(f2bf(base + want)) - base;
+      if (!F_) {
+        const float alpha = fast_exp2(-d);
         l_run[qb] *= alpha;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
           oacc[qb][0][i] *= alpha;
           oacc[qb][1][i] *= alpha;
         }
-        m_run[qb] = m_new;
       }
+      m_run[qb] = base + d;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        a[i] -= d;
+        b[i] -= d;
+      }
+      if (g == 0) negm[qb][0] = f2bf(-m_run[qb]);
       probs(qb, a, b);
     };
 
@@ -616,7 +638,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8pv_kernel(AttnParams p) 
         f32x16 r[2];
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
-          r[kb] = f32x16{};
+          r[kb] = mfma_bf16(ones8, negm[qb], f32x16{});
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             const int rr = kb * 32 + r32;

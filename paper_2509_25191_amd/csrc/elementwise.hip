@@ -66,7 +66,7 @@ hipError_t launch_layernorm(const float* x, int64_t ldx, const void* g, const vo
                  : ln_dispatch<float>(x, ldx, g, b, eps, h, ldh, rows, C, s);
 }
 
-// Row statistics in the layout the fused LayerNorm consumes: for every row
+// Row statistics in the layout ln_apply_kernel consumes: for every row
 // and every 128-column slice t, (mean_t, M2_t) = (mean of the slice, sum of
 // squared deviations from it), two passes over the slice in float32.  One
 // wave per row, two values per lane per slice.  The RESID epilogue of the
@@ -94,6 +94,50 @@ hipError_t launch_row_stats(const float* x, int64_t ldx, int rows, int C, float*
   if (rows <= 0) return hipSuccess;
   if (C % 128) return hipErrorInvalidValue;
   return launch(row_stats_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, x, ldx, rows, C, stats);
+}
+
+// LayerNorm from precomputed row statistics: h[r] = bf16((x[r] - mean) /
+// sqrt(var + eps) * g + b), with mean and the biased variance combined from
+// the (mean, M2) pairs of the row's 128-column slices (Chan et al.'s pairwise
+// update: every slice holds 128 values) at stats[(srow0 + r) * C/128 * 2].
+// The projection GEMMs' residual epilogues write those pairs for the rows
+// they update, so the statistics cost no pass of their own.  One wave per
+// row, four consecutive columns per lane and step.
+__global__ __launch_bounds__(256) void ln_apply_kernel(const float* x, int64_t ldx, const float* stats, int64_t srow0,
+                                                       const bf16* g, const bf16* b, float eps, bf16* h, int64_t ldh,
+                                                       int rows, int C) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const int nt = C / 128;
+  const float* st = stats + (srow0 + row) * nt * 2;
+  float mu = 0.f;
+  for (int t = 0; t < nt; ++t) mu += st[2 * t];
+  mu /= (float)nt;
+  float m2 = 0.f;
+  for (int t = 0; t < nt; ++t) {
+    const float d = st[2 * t] - mu;
+    m2 += st[2 * t + 1] + 128.f * d * d;
+  }
+  const float rs = 1.f / __builtin_sqrtf(m2 / (float)C + eps), nm = -mu * rs;
+  const float* xr = x + (int64_t)row * ldx;
+  bf16* hr = h + (int64_t)row * ldh;
+  for (int c = 4 * lane; c < C; c += 256) {
+    const f32x4 v = *(const f32x4*)(xr + c);
+    const bf16x4 gg = *(const bf16x4*)(g + c), bb = *(const bf16x4*)(b + c);
+    bf16x4 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = f2bf(__builtin_fmaf(__builtin_fmaf(v[j], rs, nm), bf2f(gg[j]), bf2f(bb[j])));
+    *(bf16x4*)(hr + c) = o;
+  }
+}
+
+hipError_t launch_ln_apply(const float* x, int64_t ldx, const float* stats, int64_t srow0, const void* g, const void* b,
+                           float eps, void* h, int64_t ldh, int rows, int C, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  if (C % 128) return hipErrorInvalidValue;
+  return launch(ln_apply_kernel, dim3((rows + 3) / 4), dim3(256), 0, s, x, ldx, stats, srow0, (const bf16*)g,
+                (const bf16*)b, eps, (bf16*)h, ldh, rows, C);
 }
 
 // Seeded synthetic bfloat16 values for the autotuner: a counter-based hash

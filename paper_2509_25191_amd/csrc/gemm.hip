@@ -100,9 +100,7 @@ __device__ __forceinline__ float half_wave_sum(float v) {
 // tiles (2 x 2 MFMA 32x32x16 blocks each).  A and W tiles are staged in LDS
 // with 16-byte granules XOR-swizzled by row; the accumulators go through LDS
 // once more so that the epilogue reads and writes whole rows.
-// LNA: A is LayerNorm(x), normalised from float32 rows while its tile is
-// loaded (the LayerNorm output is never stored).
-template <int EPI, bool LNA>
+template <int EPI>
 __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
   constexpr int BM = 128, BN = 128, BK = 64, CLD = BN + 4;
   __shared__ __attribute__((aligned(16))) char smem[BM * CLD * 4];
@@ -117,62 +115,15 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
   const bf16* A = (const bf16*)p.a;
   const bf16* W = (const bf16*)p.w;
   const bf16x8 zero8 = {};
-
-  // LNA: mean and 1/sqrt(var + eps) of the thread's 4 A rows, from the
-  // (mean, M2) pairs of their 128-column slices (Chan's combination; every
-  // slice has 128 values)
-  float ln_mu[4], ln_rs[4];
-  if (LNA) {
-    const int nt = p.K / 128;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = (tid >> 3) + 32 * i;
-      ln_mu[i] = 0.f;
-      ln_rs[i] = 0.f;
-      if (m0 + r < p.M) {
-        const float* st = p.stats + ((int64_t)p.row0 + m0 + r) * nt * 2;
-        float mu = 0.f;
-        for (int t = 0; t < nt; ++t) mu += st[2 * t];
-        mu /= (float)nt;
-        float m2 = 0.f;
-        for (int t = 0; t < nt; ++t) {
-          const float d = st[2 * t] - mu;
-          m2 += st[2 * t + 1] + 128.f * d * d;
-        }
-        ln_mu[i] = mu;
-        ln_rs[i] = 1.f / __builtin_sqrtf(m2 / (float)p.K + p.ln_eps);
-      }
-    }
-  }
   bf16x8 areg[4], wreg[4];
   auto gload = [&](int k0) {
     const int ch = tid & 7;
-    bf16x8 gam, bet;
-    if (LNA) {
-      gam = *(const bf16x8*)((const bf16*)p.ln_g + k0 + ch * 8);
-      bet = *(const bf16x8*)((const bf16*)p.ln_b + k0 + ch * 8);
-    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = (tid >> 3) + 32 * i;
-      if (LNA) {
-        bf16x8 h = zero8;
-        if (m0 + r < p.M) {
-          const float* xa = (const float*)p.a + (int64_t)(m0 + r) * p.lda + k0 + ch * 8;
-          const f32x4 lo = *(const f32x4*)xa, hi = *(const f32x4*)(xa + 4);
-          const float nm = -ln_mu[i] * ln_rs[i];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const float xv = j < 4 ? lo[j] : hi[j - 4];
-            h[j] = f2bf(__builtin_fmaf(__builtin_fmaf(xv, ln_rs[i], nm), bf2f(gam[j]), bf2f(bet[j])));
-          }
-        }
-        areg[i] = h;
-      } else {
-        const bf16* a = p.a_hs ? A + (k0 >> 6) * p.a_hs + (int64_t)(m0 + r) * kHeadDim + ch * 8
-                               : A + (int64_t)(m0 + r) * p.lda + k0 + ch * 8;
-        areg[i] = (m0 + r < p.M) ? *(const bf16x8*)a : zero8;
-      }
+      const bf16* a = p.a_hs ? A + (k0 >> 6) * p.a_hs + (int64_t)(m0 + r) * kHeadDim + ch * 8
+                             : A + (int64_t)(m0 + r) * p.lda + k0 + ch * 8;
+      areg[i] = (m0 + r < p.M) ? *(const bf16x8*)a : zero8;
       wreg[i] = *(const bf16x8*)(W + (int64_t)(n0 + r) * p.K + k0 + ch * 8);
     }
   };
@@ -301,23 +252,17 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmParams p) {
 
 hipError_t launch_gemm_bf16(const GemmParams& p, Epi epi, hipStream_t s) {
   dim3 grid(p.N / 128, (p.M + 127) / 128), block(256);
-  const bool ln = p.ln_g != nullptr;
-  if (ln && (epi != EPI_QKV && epi != EPI_GELU)) return hipErrorInvalidValue;
   switch (epi) {
-    case EPI_QKV:
-      return ln ? launch(gemm_bf16_kernel<EPI_QKV, true>, grid, block, 0, s, p)
-                : launch(gemm_bf16_kernel<EPI_QKV, false>, grid, block, 0, s, p);
-    case EPI_RESID: return launch(gemm_bf16_kernel<EPI_RESID, false>, grid, block, 0, s, p);
-    case EPI_GELU:
-      return ln ? launch(gemm_bf16_kernel<EPI_GELU, true>, grid, block, 0, s, p)
-                : launch(gemm_bf16_kernel<EPI_GELU, false>, grid, block, 0, s, p);
-    case EPI_EMBED: return launch(gemm_bf16_kernel<EPI_EMBED, false>, grid, block, 0, s, p);
+    case EPI_QKV: return launch(gemm_bf16_kernel<EPI_QKV>, grid, block, 0, s, p);
+    case EPI_RESID: return launch(gemm_bf16_kernel<EPI_RESID>, grid, block, 0, s, p);
+    case EPI_GELU: return launch(gemm_bf16_kernel<EPI_GELU>, grid, block, 0, s, p);
+    case EPI_EMBED: return launch(gemm_bf16_kernel<EPI_EMBED>, grid, block, 0, s, p);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_gemm_f32(const GemmParams& p, Epi epi, hipStream_t s) {
-  if (p.ln_g || p.stats) return hipErrorInvalidValue;  // the float32 path runs its LayerNorms separately
+  if (p.stats) return hipErrorInvalidValue;  // the float32 path computes its LayerNorm statistics itself
   dim3 grid(p.N / 64, (p.M + 63) / 64), block(256);
   switch (epi) {
     case EPI_QKV: return launch(gemm_f32_kernel<EPI_QKV>, grid, block, 0, s, p);

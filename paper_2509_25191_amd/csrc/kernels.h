@@ -95,14 +95,11 @@ struct GemmParams {
   void* out; int64_t ldo; int out_f32;
   // EPI_GELU: hid[r, c] = gelu(result)
   void* hid; int64_t ldh;
-  // Fused LayerNorm.  ln_g != null: A is LayerNorm(x) computed while the A
-  // tile is loaded: a (float32, leading dimension lda) holds the residual rows
-  // and stats the (mean, M2) pairs of their C/128 128-column slices (rows
-  // indexed from row0), combined per row into the mean and the biased
-  // variance; A(m, k) = (a(m, k) - mean) / sqrt(var + ln_eps) * ln_g[k] + ln_b[k].
-  // EPI_RESID with stats != null: the epilogue writes those pairs for the
-  // rows it updates (slice n0 / 128 of the output tile).
-  float* stats; const void* ln_g; const void* ln_b; float ln_eps;
+  // EPI_RESID with stats != null: the epilogue also writes, for every row it
+  // updates, the (mean, M2) pair of the new residual over its 128-column
+  // output slice, at stats[((row0 + r) * N / 128 + n0 / 128) * 2]
+  // (ln_apply_kernel combines the pairs of a row into its LayerNorm).
+  float* stats;
   // EPI_EMBED: A row m is patch i = m % emb_np of frame f = m / emb_np;
   // x[f * emb_pd + kEmbedSpecial + i, c] = result + pos[1 + i, c] (pos [.., N], bias type)
   const void* pos; int emb_np, emb_pd;
@@ -117,6 +114,9 @@ hipError_t launch_layernorm(const float* x, int64_t ldx, const void* g, const vo
 hipError_t launch_copy_f32(const float* src, float* dst, int64_t n, hipStream_t s);
 // Per-row (mean, M2) of every 128-column slice of x [rows, C] -> stats [rows, C / 128, 2]
 hipError_t launch_row_stats(const float* x, int64_t ldx, int rows, int C, float* stats, hipStream_t s);
+// h[r] = bf16 LayerNorm of x[r] from the slice statistics of row srow0 + r (g, b bf16)
+hipError_t launch_ln_apply(const float* x, int64_t ldx, const float* stats, int64_t srow0, const void* g, const void* b,
+                           float eps, void* h, int64_t ldh, int rows, int C, hipStream_t s);
 
 // ---- patch-embedding front end (embed.hip)
 constexpr int kEmbedPatch = 14;                          // patch side in pixels

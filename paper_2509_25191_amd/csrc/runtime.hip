@@ -271,7 +271,7 @@ struct Ws {
   void* v = nullptr;         // F32: [H, N, D]; BF16 / FP8: [H, rows, D] staging of V before its transposition
   bf16* vt = nullptr;        // BF16 / FP8: transposed V [H, D, vt_cols] (FP8: frame chunks only)
   void* o = nullptr;         // FP8: global attention output [H, N, D] bf16
-  void* h = nullptr;         // F32: LayerNorm output [rows, C] (BF16 / FP8 normalise inside the GEMMs)
+  void* h = nullptr;         // LayerNorm output [rows, C] (f32 or bf16), the A operand of QKV and fc1
   float* stats = nullptr;    // BF16 / FP8: per row and 128-column slice of x, (mean, M2) [N, C / 128, 2]
   void* hid = nullptr;       // MLP hidden [rows, F]
   uint8_t* q8 = nullptr;     // FP8 codes [H, N, D]
@@ -315,8 +315,8 @@ Ws carve(const vggtx_config& c, const WsShape& sh, vggtx_prec prec, char* base) 
   }
   w.v = take((prec == VGGTX_F32 ? N : R) * C * el);
   if (prec != VGGTX_F32) w.vt = (bf16*)take(C * sh.vt_cols * 2);
-  if (prec == VGGTX_F32) w.h = take(R * C * 4);
-  else w.stats = (float*)take(N * (C / 128) * 2 * 4);
+  w.h = take(R * C * el);
+  if (prec != VGGTX_F32) w.stats = (float*)take(N * (C / 128) * 2 * 4);
   w.hid = take(R * F * el);
   if (prec == VGGTX_FP8_E4M3) {
     w.o = take(N * C * 2);
@@ -392,6 +392,22 @@ inline HView hv_at(HView v, int64_t t, size_t el) { return HView{(char*)v.p + t 
 
 // Output phase over rows [r0, r1): x += O W_o^T + b_o (O read head-major from
 // `o`, whose first token is row r0); x += MLP(LN2(x)); optional output copy.
+// LayerNorm of the residual rows r0 .. r0+M-1 into the GEMM operand h.
+// BF16 / FP8: from the slice statistics the previous residual epilogue (or
+// seed_stats) wrote, so only the normalisation pass runs; F32: the two-pass
+// LayerNorm kernel.
+vggtx_status layernorm(const BlockRun& br, const void* gamma, const void* beta, int64_t r0, int M) {
+  const vggtx_config& c = br.ctx->cfg;
+  const int C = c.dim;
+  Span sp(br.ctx, VGGTX_K_OTHER, 0.0, br.stream);
+  if (lowp(br.prec))
+    VGGTX_HIP(launch_ln_apply(br.ws.x + r0 * C, C, br.ws.stats, r0, gamma, beta, c.ln_eps, br.ws.h, C, M, C,
+                              br.stream));
+  else
+    VGGTX_HIP(launch_layernorm(br.ws.x + r0 * C, C, gamma, beta, c.ln_eps, br.ws.h, C, M, C, false, br.stream));
+  return VGGTX_OK;
+}
+
 vggtx_status out_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, int64_t r1, HView o, void* out,
                        int64_t ldo, bool out_f32) {
   const vggtx_config& c = br.ctx->cfg;
@@ -414,14 +430,8 @@ vggtx_status out_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, i
     VGGTX_HIP(gemm(g, EPI_RESID, br.stream));
   }
   memset(&g, 0, sizeof(g));
-  if (lp) {  // LN2 applied while the fc1 GEMM loads x
-    g.a = br.ws.x + r0 * C; g.lda = C;
-    g.stats = br.ws.stats; g.ln_g = w.ln2_g; g.ln_b = w.ln2_b; g.ln_eps = c.ln_eps;
-  } else {
-    Span sp(br.ctx, VGGTX_K_OTHER, 0.0, br.stream);
-    VGGTX_HIP(launch_layernorm(br.ws.x + r0 * C, C, w.ln2_g, w.ln2_b, c.ln_eps, br.ws.h, C, M, C, false, br.stream));
-    g.a = br.ws.h; g.lda = C;
-  }
+  VGGTX_TRY(layernorm(br, w.ln2_g, w.ln2_b, r0, M));
+  g.a = br.ws.h; g.lda = C;
   g.w = w.w_fc1; g.bias = w.b_fc1;
   g.M = M; g.N = F; g.K = C;
   g.row0 = (int)r0;
@@ -454,14 +464,8 @@ vggtx_status qkv_phase(const BlockRun& br, const vggtx_block_w& w, int64_t r0, i
   const int M = (int)(r1 - r0);
   GemmParams g;
   memset(&g, 0, sizeof(g));
-  if (lp) {  // LN1 applied while the GEMM loads x, from the statistics the last epilogue left
-    g.a = br.ws.x + r0 * C; g.lda = C;
-    g.stats = br.ws.stats; g.ln_g = w.ln1_g; g.ln_b = w.ln1_b; g.ln_eps = c.ln_eps;
-  } else {
-    Span sp(br.ctx, VGGTX_K_OTHER, 0.0, br.stream);
-    VGGTX_HIP(launch_layernorm(br.ws.x + r0 * C, C, w.ln1_g, w.ln1_b, c.ln_eps, br.ws.h, C, M, C, false, br.stream));
-    g.a = br.ws.h; g.lda = C;
-  }
+  VGGTX_TRY(layernorm(br, w.ln1_g, w.ln1_b, r0, M));
+  g.a = br.ws.h; g.lda = C;
   g.w = w.w_qkv; g.bias = w.b_qkv;
   g.M = M; g.N = 3 * C; g.K = C;
   g.row0 = (int)r0;
