@@ -843,14 +843,17 @@ __device__ __forceinline__ i32x8 probs(const f32x16& a, const f32x16& b) {
 // of parity j&1, E4M3 1.0 or 0) makes output lane l, which holds rows
 // 4*(l/16)+i, receive the sum for its own query l%32 in all four registers.
 //
-// LDS: Ks[key][d] bytes, 16-byte granules swizzled with lds_swz4(key);
-//      Vs[d][key'] bytes, keys of every 32-key block permuted so that lane
-//      group g finds its 16 k-slots in one granule (slot j of group g <->
-//      key 32*(j/16) + 8*((j%16)/4) + 4*g + j%4), granules swizzled with
-//      lds_swz4(d).
+// LDS: Ks[row][d] bytes and Vs[d][key] bytes (V^T in key order), 16-byte
+//      granules swizzled with lds_swz4(row) and lds_swz4(d), both filled by
+//      direct-to-LDS loads.  The K rows of each 32-row block are permuted
+//      (row 32 kb + r holds key 32 ((r >> 2) & 1) + 16 kb + 4 (r >> 3) + (r & 3))
+//      so that the score registers of lane group g hold the 32 consecutive
+//      keys 32 g .. 32 g + 31, the keys whose V^T bytes the same group reads
+//      from granules 2 g and 2 g + 1 of a V^T row: P goes from the score
+//      accumulator to the P V operand with no permutation.
 template <int QB, int NW, int OCC>
 __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
-  constexpr int BN = 64, D = kHeadDim, BM = 32 * QB * NW, NT = 64 * NW;
+  constexpr int BN = 64, D = kHeadDim, BM = 32 * QB * NW;
   constexpr float kLog2Max = 8.80735492205760410745f;  // log2(448)
   // a rescale places the row maximum this many binades below 448, so that
   // later tiles may raise it by up to a factor 2^kHeadroom without overflow
@@ -886,49 +889,28 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
     eq[qb] = (int)(__float_as_uint(SQ[(it.q0 - it.s0 + (wave * QB + qb) * 32) / kQuantRows]) >> 23);
   }
 
-  // K tile: 64 keys x 64 B; V tile: 64 d x 64 B; 512 granules of 16 B
-  constexpr int LPT = 512 / NT;  // granules per thread
-  i32x4 reg[LPT];
-  // granule gi of a tile: K (gi < 256) or V (gi >= 256), row (gi / 4) % 64,
-  // 16-byte chunk gi % 4; per-thread source of tile 0 and per-tile step
-  const uint8_t* src[LPT];
-  int64_t step[LPT];
+  // Tile t into LDS buffer buf: 4 blocks of 16 K rows and 4 blocks of 16 V^T
+  // rows (64 B each, 1 KB per block); wave w moves blocks w, w + NW, ...
+  // (blocks 0-3 K, 4-7 V^T).  K rows permuted so that each lane group's
+  // score registers hold 32 consecutive keys (LDS row 32 kb + r holds key
+  // 32 ((r >> 2) & 1) + 16 kb + 4 (r >> 3) + (r & 3)); V^T in key order.
+  auto dma = [&](int t, int buf) {
+    const int rows_left = it.s1 - (it.s0 + t * BN);
 #pragma unroll
-  for (int i = 0; i < LPT; ++i) {
-    const int gi = tid + NT * i;
-    const int r = (gi >> 2) & 63, ch = gi & 3;
-    if (gi < 256) {
-      src[i] = K + (int64_t)(it.s0 + r) * p.k_ts + ch * 16;
-      step[i] = (int64_t)BN * p.k_ts;
-    } else {
-      src[i] = Vt + r * p.vt_ds + ch * 16;
-      step[i] = BN;
-    }
-  }
-  auto gload = [&](int t) {
-    const i32x4 z = {};
-    const int rows_left = it.s1 - (it.s0 + t * BN);  // keys of this tile that exist
-#pragma unroll
-    for (int i = 0; i < LPT; ++i) {
-      const int gi = tid + NT * i;
-      const int r = (gi >> 2) & 63;
-      const i32x4* a = (const i32x4*)(src[i] + t * step[i]);
-      reg[i] = (gi >= 256 || r < rows_left) ? *a : z;
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < LPT; ++i) {
-      const int gi = tid + NT * i;
-      const int isv = gi >> 8, r = (gi >> 2) & 63, ch = gi & 3;
-      const int sw = lds_swz4(r);
-      if (!isv) {
-        *(i32x4*)&Ks[buf][r * D + ((ch ^ sw) * 16)] = reg[i];
-      } else {
-        const int kb = ch >> 1, h = ch & 1;
-        const i32x2 a = {reg[i][0], reg[i][2]}, b = {reg[i][1], reg[i][3]};
-        *(i32x2*)&Vs[buf][r * BN + (((2 * kb) ^ sw) * 16) + 8 * h] = a;
-        *(i32x2*)&Vs[buf][r * BN + (((2 * kb + 1) ^ sw) * 16) + 8 * h] = b;
+    for (int j = 0; j < (8 + NW - 1) / NW; ++j) {
+      const int b = wave + NW * j;
+      if (b < 4) {
+        const int R = 16 * b + (lane >> 2), ch = (lane & 3) ^ lds_swz4(R);
+        const int r = R & 31;
+        const int key = 32 * ((r >> 2) & 1) + 16 * (R >> 5) + 4 * (r >> 3) + (r & 3);
+        const int kr = key < rows_left ? key : 0;  // rows past the end: any existing key (masked)
+        __builtin_amdgcn_global_load_lds((const void*)(K + (int64_t)(it.s0 + t * BN + kr) * p.k_ts + ch * 16),
+                                         (__attribute__((address_space(3))) void*)&Ks[buf][16 * b * D], 16, 0, 0);
+      } else if (b < 8) {
+        const int d = 16 * (b - 4) + (lane >> 2), ch = (lane & 3) ^ lds_swz4(d);
+        __builtin_amdgcn_global_load_lds((const void*)(Vt + (int64_t)d * p.vt_ds + t * BN + ch * 16),
+                                         (__attribute__((address_space(3))) void*)&Vs[buf][16 * (b - 4) * BN], 16,
+                                         0, 0);
       }
     }
   };
@@ -946,8 +928,8 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
     lacc[qb] = f32x4{};
   }
   const int ntiles = (it.s1 - it.s0 + BN - 1) / BN;
-  gload(0);
-  lstore(0);
+  dma(0, 0);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   // One key tile.  MASKED is set only for the final, partial tile of a
   // sequence, so full tiles carry no key-bound checks; FIRST only for the
@@ -957,7 +939,6 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
     constexpr bool MASKED = decltype(masked)::value, FIRST = decltype(first)::value;
     constexpr bool EXACT = MASKED || FIRST;
     const int kt = it.s0 + t * BN, buf = t & 1;
-    if (t + 1 < ntiles) gload(t + 1);
     i32x8 kf[2];
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
@@ -987,7 +968,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
         for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
           for (int i = 0; i < 16; ++i)
-            if (kt + kb * 32 + 8 * (i >> 2) + 4 * g + (i & 3) >= it.s1) (kb ? b : a)[i] = -INFINITY;
+            if (kt + 32 * g + 16 * kb + i >= it.s1) (kb ? b : a)[i] = -INFINITY;
       }
       const float xmax = lane_swap_max(max32(a, b));
       if (FIRST || __any(xmax > kLog2Max)) {
@@ -1034,10 +1015,12 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
 #pragma unroll
         for (int db = 0; db < 2; ++db) {
           const int d = db * 32 + r32, sw = lds_swz4(d);
-          const i32x4 lo = *(const i32x4*)&Vs[buf][d * BN + ((g ^ sw) * 16)];
-          const i32x4 hi = *(const i32x4*)&Vs[buf][d * BN + (((2 + g) ^ sw) * 16)];
+          const i32x4 lo = *(const i32x4*)&Vs[buf][d * BN + (((2 * g) ^ sw) * 16)];
+          const i32x4 hi = *(const i32x4*)&Vs[buf][d * BN + (((2 * g + 1) ^ sw) * 16)];
           vf[db] = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
         }
+        // every LDS read of this tile's fragments is issued: move the next tile in
+        if (t + 1 < ntiles) dma(t + 1, buf ^ 1);
       }
       // full tiles after the first: probabilities against the current m; a
       // NaN code makes the row sum NaN (tested on the bits, not with a float
@@ -1062,7 +1045,7 @@ __global__ __launch_bounds__(64 * NW, OCC) void attn_fp8_kernel(AttnParams p) {
     pv(QB - 1);
     __builtin_amdgcn_sched_barrier(0);
     if (t + 1 < ntiles) {
-      lstore(buf ^ 1);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
     }
   };
