@@ -11,6 +11,8 @@
 #include "common.h"
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace vggtx {
 
 __device__ __forceinline__ float gelu_erf(float u) { return 0.5f * u * (1.f + erff(u * 0.70710678118654752f)); }
@@ -100,6 +102,17 @@ __device__ __forceinline__ float half_wave_sum(float v) {
 // tiles (2 x 2 MFMA 32x32x16 blocks each).  A and W tiles are staged in LDS
 // with 16-byte granules XOR-swizzled by row; the accumulators go through LDS
 // once more so that the epilogue reads and writes whole rows.
+//
+// Pipeline: the global loads run two K tiles ahead through two register
+// sets (tile j in set j % 2), the stores of tile kt + 1 into the other LDS
+// buffer follow the MFMAs of tile kt, and within a tile the LDS reads of
+// k-step kk + 1 are issued before the MFMAs of k-step kk (scheduling
+// barriers keep that order).  Control flow is uniform, so the compiler's
+// load counters never have to assume a path without loads: rows past M read
+// row M - 1 (their results are never stored), the loads past the last tile
+// repeat it, and the final store goes to the buffer nobody reads any more.
+// The barrier between tiles is a plain s_barrier after the LDS stores:
+// __syncthreads() would also wait for the loads still in flight.
 template <int EPI>
 __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
   constexpr int BM = 128, BN = 128, BK = 64, CLD = BN + 4;
@@ -112,28 +125,39 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
   const int g = lane >> 5, r32 = lane & 31;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  const bf16* A = (const bf16*)p.a;
-  const bf16* W = (const bf16*)p.w;
-  const bf16x8 zero8 = {};
-  bf16x8 areg[4], wreg[4];
-  auto gload = [&](int k0) {
-    const int ch = tid & 7;
+  const int ch = tid & 7;
+  const int64_t a_rs = p.a_hs ? kHeadDim : p.lda;  // A row stride
+  const int64_t a_ts = p.a_hs ? p.a_hs : BK;       // A step per K tile
+  const bf16* asrc[4];
+  const bf16* wsrc[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = (tid >> 3) + 32 * i;
+    asrc[i] = (const bf16*)p.a + min(m0 + r, p.M - 1) * a_rs + ch * 8;
+    wsrc[i] = (const bf16*)p.w + (int64_t)(n0 + r) * p.K + ch * 8;
+  }
+  bf16x8 areg[2][4], wreg[2][4];
+  auto gload = [&](auto set_c, int kt) {
+    constexpr int SET = decltype(set_c)::value;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      areg[SET][i] = *(const bf16x8*)(asrc[i] + kt * a_ts);
+      wreg[SET][i] = *(const bf16x8*)(wsrc[i] + kt * BK);
+    }
+  };
+  auto lstore = [&](auto set_c, int buf) {
+    constexpr int SET = decltype(set_c)::value;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = (tid >> 3) + 32 * i;
-      const bf16* a = p.a_hs ? A + (k0 >> 6) * p.a_hs + (int64_t)(m0 + r) * kHeadDim + ch * 8
-                             : A + (int64_t)(m0 + r) * p.lda + k0 + ch * 8;
-      areg[i] = (m0 + r < p.M) ? *(const bf16x8*)a : zero8;
-      wreg[i] = *(const bf16x8*)(W + (int64_t)(n0 + r) * p.K + k0 + ch * 8);
+      *(bf16x8*)&As[buf * BM * BK + r * BK + ((ch ^ lds_swz8(r)) * 8)] = areg[SET][i];
+      *(bf16x8*)&Ws[buf * BN * BK + r * BK + ((ch ^ lds_swz8(r)) * 8)] = wreg[SET][i];
     }
   };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = (tid >> 3) + 32 * i, ch = tid & 7;
-      *(bf16x8*)&As[buf * BM * BK + r * BK + ((ch ^ lds_swz8(r)) * 8)] = areg[i];
-      *(bf16x8*)&Ws[buf * BN * BK + r * BK + ((ch ^ lds_swz8(r)) * 8)] = wreg[i];
-    }
+  auto barrier = [&]() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
   };
 
   f32x16 acc[2][2];
@@ -142,34 +166,65 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16_kernel(GemmParams p) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
 
+  using S0 = std::integral_constant<int, 0>;
+  using S1 = std::integral_constant<int, 1>;
   const int nk = p.K / BK;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
+  gload(S0{}, 0);
+  gload(S1{}, min(1, nk - 1));
+  lstore(S0{}, 0);
+  barrier();
+  // step kt: tile kt + 2 -> register set SET (= kt % 2), MFMAs on LDS buffer
+  // kt & 1, tile kt + 1 (set 1 - SET) -> the other buffer
+  auto step = [&](int kt, auto set_c) {
+    constexpr int SET = decltype(set_c)::value;
     const int buf = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BK);
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      bf16x8 a[2], b[2];
+    gload(set_c, min(kt + 2, nk - 1));
+    __builtin_amdgcn_sched_barrier(0);
+    bf16x8 a[2][2], b[2][2];  // operands of k-step kk in set kk & 1
+    auto rd = [&](int kk, auto s_c) {
+      constexpr int S = decltype(s_c)::value;
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi) {
         const int r = wm * 64 + mi * 32 + r32;
-        a[mi] = *(const bf16x8*)&As[buf * BM * BK + r * BK + (((2 * kk + g) ^ lds_swz8(r)) * 8)];
+        a[S][mi] = *(const bf16x8*)&As[buf * BM * BK + r * BK + (((2 * kk + g) ^ lds_swz8(r)) * 8)];
       }
 #pragma unroll
       for (int nj = 0; nj < 2; ++nj) {
         const int r = wn * 64 + nj * 32 + r32;
-        b[nj] = *(const bf16x8*)&Ws[buf * BN * BK + r * BK + (((2 * kk + g) ^ lds_swz8(r)) * 8)];
+        b[S][nj] = *(const bf16x8*)&Ws[buf * BN * BK + r * BK + (((2 * kk + g) ^ lds_swz8(r)) * 8)];
       }
+    };
+    auto mm = [&](auto s_c) {
+      constexpr int S = decltype(s_c)::value;
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = mfma_bf16(a[mi], b[nj], acc[mi][nj]);
-    }
-    if (kt + 1 < nk) lstore(buf ^ 1);
-    __syncthreads();
+        for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = mfma_bf16(a[S][mi], b[S][nj], acc[mi][nj]);
+    };
+    rd(0, S0{});
+    rd(1, S1{});
+    __builtin_amdgcn_sched_barrier(0);
+    mm(S0{});
+    __builtin_amdgcn_sched_barrier(0);
+    rd(2, S0{});
+    __builtin_amdgcn_sched_barrier(0);
+    mm(S1{});
+    __builtin_amdgcn_sched_barrier(0);
+    rd(3, S1{});
+    __builtin_amdgcn_sched_barrier(0);
+    mm(S0{});
+    __builtin_amdgcn_sched_barrier(0);
+    mm(S1{});
+    lstore(std::integral_constant<int, 1 - SET>{}, buf ^ 1);
+    barrier();
+  };
+  int kt = 0;
+  for (; kt + 2 <= nk; kt += 2) {
+    step(kt, S0{});
+    step(kt + 1, S1{});
   }
+  if (kt < nk) step(kt, S0{});
+  __syncthreads();
 
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
@@ -251,6 +306,7 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(GemmParams p) {
 }
 
 hipError_t launch_gemm_bf16(const GemmParams& p, Epi epi, hipStream_t s) {
+  if (p.M <= 0) return hipSuccess;  // nothing to compute (the kernel reads row M - 1)
   dim3 grid(p.N / 128, (p.M + 127) / 128), block(256);
   switch (epi) {
     case EPI_QKV: return launch(gemm_bf16_kernel<EPI_QKV>, grid, block, 0, s, p);
