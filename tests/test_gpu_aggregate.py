@@ -52,6 +52,31 @@ def test_block_parity(prec, tol, std):
     assert e < tol
 
 
+@pytest.mark.parametrize("prec,tol", [(vg.F32, 1e-4), (vg.BF16, 2e-2), (vg.FP8_E4M3, 6e-2), (vg.FP8_PV, 6e-2)])
+@pytest.mark.parametrize("offs", [[0, 1], [0, 1, 6, 7]])
+def test_block_parity_tiny_sequences(prec, tol, offs):
+    """A block over one token, and over sequences of 1, 5 and 1 tokens: the
+    projection GEMMs run on 1 and 7 rows of a 128-row tile (rows past the
+    end read the last row and are never stored), attention runs on one-key
+    sequences and the FP8 scale blocks hold one to five rows."""
+    m = SMALL
+    rng = np.random.default_rng(12)
+    w = synth.gen_block(rng, m.dim, m.mlp_hidden, std=0.02, bf16=prec != vg.F32)
+    x = rng.standard_normal((offs[-1], m.dim)).astype(np.float32)
+    ref = oracle.block(x, w, list(zip(offs[:-1], offs[1:])), m.heads, m.ln_eps)
+    h = _handle(m)
+    xd = to_dev(x, torch.float32)
+    yd = torch.empty_like(xd)
+    vg.block(h.h, xd, yd, offs, {k: to_dev(v, _dt(prec)) for k, v in w.items()}, prec)
+    torch.cuda.synchronize()
+    got = yd.cpu().numpy()
+    e = max_abs_rel(got, ref)
+    ei = max_abs_rel(got - x, ref - x)
+    print(f"tiny block prec={prec} offs={offs} out={e:.3e} increment={ei:.3e}")
+    assert np.isfinite(got).all()
+    assert e < tol
+
+
 @pytest.mark.parametrize("prec,tol,out_dtype", [(vg.F32, 1e-4, vg.OUT_F32), (vg.BF16, 2e-2, vg.OUT_BF16),
                                                 (vg.BF16, 2e-2, vg.OUT_F32), (vg.FP8_E4M3, 6e-2, vg.OUT_BF16),
                                                 (vg.FP8_PV, 6e-2, vg.OUT_F32)])
