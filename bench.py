@@ -241,7 +241,7 @@ def bench_embed(args, dev):
         "metric": "front-end frames/s (per-frame patch embedding + 24 ViT-L/14 blocks at 518x518)",
         "value": S * args.steps / sec, "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": sec * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16", "data": "synthetic (images N(0,1), weights N(0,0.02), seeded, device-generated)",
+        "dtype": {"bf16": "bf16", "fp8pv": "bf16 scores, e4m3 P V", "fp8": "e4m3"}[head], "data": "synthetic (images N(0,1), weights N(0,0.02), seeded, device-generated)",
         "config": {"workload": f"vitl14_frontend_S{S}_{Hi}x{Wi}", "frames": S, "image": [Hi, Wi],
                    "tokens_per_frame": P, "dim": model.dim, "heads": model.heads, "mlp_hidden": model.mlp_hidden,
                    "depth": depth, "frame_chunk": model.frame_chunk},
@@ -584,21 +584,22 @@ def bench_aggregator(args, dev):
     steps, warmup = plan_steps(args.steps, args.warmup, est, args.wall_budget - elapsed - args.reserve - extra)
     log(f"setup done at {elapsed:.0f}s; estimated {est:.1f}s per step; running {warmup} warm-up + {steps} timed "
         f"step(s) (requested {args.warmup} + {args.steps})")
-    sec, tm, peak = run_forward(h.h, tokens, layers, vg.BF16, out, ws, steps, warmup, "bf16", draw)
+    head = args.headline
+    sec, tm, peak = run_forward(h.h, tokens, layers, lowp[head], out, ws, steps, warmup, head, draw)
     step_s = sec / steps
     ga_tf = attn_rate(tm)
     ga = tm["attn_global"]
-    per_prec = {"bf16": {"frames_per_s": S * steps / sec, "ms_per_step": step_s * 1e3, "global_attn_tflops": ga_tf,
-                         "global_attn_frac_of_peak": ga_tf / PEAK_TFLOPS["bf16"] if ga_tf else None,
-                         "peak_hbm_gb": peak, "kernel_time_ms": {k: v["ms"] for k, v in tm.items()
-                                                                 if isinstance(v, dict)}}}
+    per_prec = {head: {"frames_per_s": S * steps / sec, "ms_per_step": step_s * 1e3, "global_attn_tflops": ga_tf,
+                       "global_attn_frac_of_peak": ga_tf / PEAK_TFLOPS[head] if ga_tf else None,
+                       "peak_hbm_gb": peak, "kernel_time_ms": {k: v["ms"] for k, v in tm.items()
+                                                               if isinstance(v, dict)}}}
     # FP8 forwards while they fit (their steps take about as long as the global attention's share allows);
     # a mode whose forward does not fit gets the rate of one standalone 16-head global attention launch
     standalone = []
-    for name in [n for n in lowp if n != "bf16"]:
+    for name in [n for n in lowp if n != head]:
         if args.no_extra:
             break
-        guess = step_s * (0.75 if name == "fp8" else 0.85)
+        guess = step_s * {"bf16": 1.0, "fp8pv": 0.85, "fp8": 0.75}[name] / {"bf16": 1.0, "fp8pv": 0.85, "fp8": 0.75}[head]
         left = args.wall_budget - (time.perf_counter() - T_START) - args.reserve
         if guess > left:
             per_prec[name] = {"forward_skipped": f"wall budget: about {guess:.0f}s needed, {left:.0f}s left"}
@@ -650,10 +651,10 @@ def bench_aggregator(args, dev):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": {"bf16": "bf16", "fp8pv": "bf16 scores, e4m3 P V", "fp8": "e4m3"}[head],
         "data": "synthetic (tokens N(0,1) drawn on the device with a fixed seed before every forward, which runs "
                 "its residual stream in that buffer; weights N(0,0.02), seeded)",
-        "config": {"workload": f"vggt_l_aggregator_S{S}_P{P}_bf16", "frames": S, "tokens_per_frame": P,
+        "config": {"workload": f"vggt_l_aggregator_S{S}_P{P}_{head}", "frames": S, "tokens_per_frame": P,
                    "global_tokens": S * P, "dim": model.dim, "heads": model.heads, "head_dim": model.head_dim,
                    "mlp_hidden": model.mlp_hidden, "depth": model.depth, "out_layers": list(OUT_LAYERS),
                    "frame_chunk": model.frame_chunk, "attn_schedule": args.schedule},
@@ -662,13 +663,13 @@ def bench_aggregator(args, dev):
         "peak_hbm_gb": peak,
         "precisions": per_prec,
         "roofline": {
-            "kernel": "attn_bf16_kernel (global attention)",
+            "kernel": f"attn_{head}_kernel (global attention)",
             "bound": "mfma",
             "achieved": ga_tf,
-            "peak": PEAK_TFLOPS["bf16"],
+            "peak": PEAK_TFLOPS[head],
             "unit": "TFLOP/s",
-            "frac": (ga_tf / PEAK_TFLOPS["bf16"]) if ga_tf else None,
-            "traffic": measured_traffic("bf16", S),
+            "frac": (ga_tf / PEAK_TFLOPS[head]) if ga_tf else None,
+            "traffic": measured_traffic(head, S),
             "flops_per_launch": ga["flops"] / max(1, ga["launches"]),
             "avg_launch_ms": avg_ms,
             "launches": ga["launches"],
@@ -751,7 +752,7 @@ def bench_varlen(args, dev):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": {"bf16": "bf16", "fp8pv": "bf16 scores, e4m3 P V", "fp8": "e4m3"}[head],
         "data": "synthetic (tokens N(0,1) drawn on the device with a fixed seed before every forward; "
                 "weights N(0,0.02), seeded)",
         "config": {"workload": f"vggt_l_varlen{len(frames)}_bf16", "scene_frames": list(frames), "frames": S,
@@ -781,6 +782,8 @@ def main():
     ap.add_argument("--assumed-tflops", type=float, default=1000.0,
                     help="forward rate assumed when planning steps before any has run")
     ap.add_argument("--no-extra", action="store_true", help="skip the FP8 forwards, the FP32 rate and the accuracy check")
+    ap.add_argument("--headline", choices=["bf16", "fp8pv", "fp8"], default="bf16",
+                    help="precision of the timed forward (the others run as extra legs); bf16 is the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",

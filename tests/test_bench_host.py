@@ -21,17 +21,22 @@ def _kv(path):
 
 def test_traffic_lookup_only_for_the_profiled_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("bf16", 200) is None  # counters exist for S=1000 only
-    assert bench.measured_traffic("fp8", 1000) is None  # and for the BF16 kernel only
-    prof = os.path.join(bench.ROOT, "profiles", "attn_bf16_kernel_vggt_l_s1000_traffic.txt")
+    assert bench.measured_traffic("fp8pv", 1000) is None  # and not for the FP8 P V kernel
     src = os.path.join(bench.ROOT, "paper_2509_25191_amd", "csrc", "attention.hip")
-    kv = _kv(prof)
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    got = bench.measured_traffic("bf16", 1000)
-    if kv["attention_hip_sha256"] == digest:
-        assert got == float(kv["hbm_bytes_per_launch"]) and got > 0
-        assert abs(got - float(kv["fetch_bytes_per_launch"]) - float(kv["write_bytes_per_launch"])) <= 1e-6 * got
-    else:
-        assert got is None
+    for prec in ("bf16", "fp8"):
+        path = os.path.join(bench.ROOT, "profiles", f"attn_{prec}_kernel_vggt_l_s1000_traffic.txt")
+        if not os.path.exists(path):
+            assert bench.measured_traffic(prec, 1000) is None
+            continue
+        kv = _kv(path)
+        got = bench.measured_traffic(prec, 1000)
+        if kv["attention_hip_sha256"] == digest:
+            assert got == float(kv["hbm_bytes_per_launch"]) and got > 0
+            assert abs(got - float(kv["fetch_bytes_per_launch"]) - float(kv["write_bytes_per_launch"])) <= 1e-6 * got
+        else:
+            assert got is None
+    prof = os.path.join(bench.ROOT, "profiles", "attn_bf16_kernel_vggt_l_s1000_traffic.txt")
     # the same summary next to a different attention source is ignored
     (tmp_path / "profiles").mkdir()
     (tmp_path / "paper_2509_25191_amd" / "csrc").mkdir(parents=True)
